@@ -1,0 +1,198 @@
+"""Pins of the oracle's stencil and normal operator against facts the mathematics fixes.
+
+* anti-Hermiticity of the staggered hopping term D (D^H = -D);
+* A = 4 m^2 - D_eo D_oe Hermitian positive definite with lambda_min >= 4 m^2;
+* free-field closed form: with unit links every even-site plane wave is an
+  eigenvector of A with eigenvalue 4 m^2 + 4 sum_mu g(p_mu)^2, g = sin p (naive)
+  or sin p + sin 3p (improved) -- this fixes the staggered phases, the signs
+  of both hops, the three-hop reach and the mass term;
+* the exact spectrum of the naive 4^4 free operator, 4 m^2 + 4 j (j = 0..4) with
+  multiplicities 24, 96, 144, 96, 24;
+* gauge covariance under random SU(3) transformations, which fixes where each
+  link sits (U_mu(x) forward, U_mu(x - k mu)^H backward);
+* the checkerboard hops against the full-lattice D restricted to one parity.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1710_09745_amd import synth
+
+
+def coords(dims):
+    """Site coordinates in lex order (x fastest), shape [V][4]."""
+    Lx, Ly, Lz, Lt = dims
+    t, z, y, x = np.meshgrid(np.arange(Lt), np.arange(Lz), np.arange(Ly), np.arange(Lx),
+                             indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel(), t.ravel()], axis=1)
+
+
+def parity_split(dims):
+    c = coords(dims)
+    par = c.sum(axis=1) % 2
+    lex = np.arange(c.shape[0])
+    even = lex[par == 0]
+    odd = lex[par == 1]
+    # cb index = lex >> 1 orders each parity by lex
+    assert np.all(even // 2 == np.arange(even.size))
+    assert np.all(odd // 2 == np.arange(odd.size))
+    return even, odd
+
+
+def random_links(seed, dims, improved):
+    r = synth.make_rng(seed)
+    fat = synth.fat_links(r, dims)
+    lng = synth.long_links(r, dims) if improved else None
+    return fat, lng
+
+
+def dense_A(op):
+    """A as a dense matrix, assembled column by column from the oracle's apply."""
+    n = op.Vh * 3
+    cols = np.eye(n, dtype=np.complex128).reshape(n, op.Vh, 3)
+    out = op.apply(cols)          # [n][Vh][3] = A e_j
+    return out.reshape(n, n).T
+
+
+@pytest.mark.parametrize("dims,improved", [((2, 2, 2, 2), False), ((4, 4, 4, 4), True),
+                                           ((6, 4, 2, 4), True), ((4, 2, 4, 6), False)])
+def test_D_antihermitian(dims, improved):
+    fat, lng = random_links(11, dims, improved)
+    op = oracle.Operator(dims, fat, lng)
+    r = synth.make_rng(12)
+    V = op.V
+    u = synth.gaussian_complex(r, (V, 3))
+    v = synth.gaussian_complex(r, (V, 3))
+    lhs = np.vdot(u, op.dslash_full(v))
+    rhs = -np.vdot(op.dslash_full(u), v)
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + 1.0)
+
+
+@pytest.mark.parametrize("dims,improved", [((4, 4, 4, 4), False), ((4, 4, 2, 4), True)])
+def test_A_hermitian_positive_definite(dims, improved):
+    m = 0.07
+    fat, lng = random_links(21, dims, improved)
+    op = oracle.Operator(dims, fat, lng, m)
+    A = dense_A(op)
+    assert np.abs(A - A.conj().T).max() <= 1e-13 * np.abs(A).max()
+    ev = np.linalg.eigvalsh(A)
+    assert ev.min() >= 4 * m * m * (1 - 1e-10)
+
+
+def plane_wave_even(dims, p, colour_vec):
+    """e^{i p.x} on the even sites (cb order) times a colour vector, [1][V/2][3]."""
+    even, _ = parity_split(dims)
+    c = coords(dims)[even]
+    ph = np.exp(1j * (c @ np.asarray(p)))
+    return (ph[:, None] * colour_vec[None, :])[None]
+
+
+@pytest.mark.parametrize("dims,improved", [((4, 4, 4, 4), False), ((6, 6, 6, 6), True),
+                                           ((8, 4, 6, 6), True), ((6, 8, 4, 2), False)])
+def test_free_field_plane_waves(dims, improved):
+    m = 0.13
+    V = synth.volume(dims)
+    op = oracle.Operator(dims, synth.unit_links(dims)[:, :V],
+                         synth.unit_links(dims) if improved else None, m)
+    r = synth.make_rng(31)
+    cvec = synth.gaussian_complex(r, (3,))
+    for n in itertools.islice(itertools.product(*[range(L) for L in dims]), 0, None, 7):
+        p = 2 * np.pi * np.asarray(n) / np.asarray(dims)
+        g = np.sin(p) + (np.sin(3 * p) if improved else 0.0)
+        lam = 4 * m * m + 4 * np.sum(g * g)
+        f = plane_wave_even(dims, p, cvec)
+        Af = op.apply(f)
+        assert np.abs(Af - lam * f).max() <= 1e-12 * max(1.0, lam)
+
+
+def test_free_field_naive_4444_spectrum():
+    m = 0.1
+    dims = (4, 4, 4, 4)
+    op = oracle.Operator(dims, synth.unit_links(dims), None, m)
+    ev = np.sort(np.linalg.eigvalsh(dense_A(op)))
+    expect = np.concatenate([np.full(k, 4 * m * m + 4 * j)
+                             for j, k in enumerate([24, 96, 144, 96, 24])])
+    assert ev.size == 384
+    assert np.abs(ev - expect).max() <= 1e-12
+
+
+def gauge_rotate(dims, fat, lng, g):
+    """U_mu(x) -> g(x) U_mu(x) g(x + k mu)^H for k = 1 (fat) and 3 (long)."""
+    c = coords(dims)
+
+    def shifted(mu, k):
+        y = c.copy()
+        y[:, mu] = (y[:, mu] + k) % dims[mu]
+        return y[:, 0] + dims[0] * (y[:, 1] + dims[1] * (y[:, 2] + dims[2] * y[:, 3]))
+
+    def rot(U, k):
+        out = np.empty_like(U)
+        for mu in range(4):
+            out[mu] = g @ U[mu] @ g[shifted(mu, k)].conj().transpose(0, 2, 1)
+        return out
+
+    return rot(fat, 1), (rot(lng, 3) if lng is not None else None)
+
+
+@pytest.mark.parametrize("dims,improved", [((4, 4, 4, 4), False), ((6, 4, 4, 6), True),
+                                           ((8, 8, 6, 4), True)])
+def test_gauge_covariance(dims, improved):
+    m = 0.05
+    fat, lng = random_links(41, dims, improved)
+    g = synth.gauge_transform(synth.make_rng(42), dims)
+    fat2, lng2 = gauge_rotate(dims, fat, lng, g)
+    op1 = oracle.Operator(dims, fat, lng, m)
+    op2 = oracle.Operator(dims, fat2, lng2, m)
+    even, odd = parity_split(dims)
+    psi = synth.rhs(synth.make_rng(43), 2, dims)
+    gpsi = np.einsum("sab,nsb->nsa", g[even], psi)
+    lhs = op2.apply(gpsi)
+    rhs = np.einsum("sab,nsb->nsa", g[even], op1.apply(psi))
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+    # the odd-parity hop transforms with g on the odd sites
+    lhs = op2.hop(1, gpsi)
+    rhs = np.einsum("sab,nsb->nsa", g[odd], op1.hop(1, psi))
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+
+
+@pytest.mark.parametrize("dims,improved", [((4, 4, 4, 4), True), ((2, 4, 6, 2), False),
+                                           ((6, 2, 4, 4), True)])
+def test_hops_match_full_lattice(dims, improved):
+    fat, lng = random_links(51, dims, improved)
+    op = oracle.Operator(dims, fat, lng, 0.3)
+    even, odd = parity_split(dims)
+    r = synth.make_rng(52)
+    for out_par, (src_sites, dst_sites) in [(1, (even, odd)), (0, (odd, even))]:
+        v = synth.gaussian_complex(r, (2, op.Vh, 3))
+        got = op.hop(out_par, v)
+        for i in range(2):
+            full = np.zeros((op.V, 3), dtype=np.complex128)
+            full[src_sites] = v[i]
+            out = op.dslash_full(full)
+            assert np.abs(out[src_sites]).max() == 0.0     # D only connects opposite parities
+            assert np.abs(got[i] - out[dst_sites]).max() <= 1e-13 * np.abs(out).max()
+    # A = 4 m^2 - D_eo D_oe
+    v = synth.gaussian_complex(r, (3, op.Vh, 3))
+    expect = 4 * 0.3 ** 2 * v - op.hop(0, op.hop(1, v))
+    assert np.abs(op.apply(v) - expect).max() <= 1e-13 * np.abs(expect).max()
+
+
+@pytest.mark.parametrize("dims,improved", [((4, 4, 4, 4), True), ((6, 4, 4, 8), True),
+                                           ((4, 4, 4, 4), False)])
+def test_apply_at_sites_matches_apply(dims, improved):
+    fat, lng = random_links(61, dims, improved)
+    op = oracle.Operator(dims, fat, lng, 0.11)
+    v = synth.rhs(synth.make_rng(62), 3, dims)
+    sites = synth.make_rng(63).choice(op.Vh, size=17, replace=False)
+    full = op.apply(v)
+    part = op.apply_sites(v, sites)
+    assert np.abs(part - full[:, sites]).max() <= 1e-13 * np.abs(full).max()
+
+
+def test_haar_links_are_su3():
+    u = synth.haar_su3(synth.make_rng(71), (50,))
+    eye = np.eye(3)
+    assert np.abs(u @ u.conj().transpose(0, 2, 1) - eye).max() < 1e-13
+    assert np.abs(np.linalg.det(u) - 1).max() < 1e-13

@@ -1,0 +1,242 @@
+"""Pins of the oracle's blockCGrQ, thin QR, reliable updates and CG.
+
+* library routines: dense Cholesky solve (numpy) for X = A^{-1} B; numpy's
+  Householder QR (phase-fixed) for the CholQR factors; numpy's inverse for the
+  HPD inverse;
+* special case: N = 1 blockCGrQ is CG (Sec. 4): same iterates, C_k = ||r_k||;
+* closed form: the naive free 4^4 operator has 5 distinct eigenvalues, so any
+  Krylov method finishes in at most 5 iterations;
+* invariants of blockCGrQ: Q^H Q = I, Q_k^H P_k = I (kept through reliable
+  updates), block A-conjugacy P_j^H A P_k = 0, and the iterated residual norms
+  (C^H H C)_ii equal the true residual norms;
+* a reliable update is a no-op in exact arithmetic: with FP64 "sloppy"
+  storage the iteration count and solution match the plain solve;
+* breakdown on linearly dependent columns, error on a zero column.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1710_09745_amd import synth
+
+from test_oracle_operator import dense_A
+
+
+def small_problem(dims=(4, 4, 4, 4), improved=True, m=0.1, n=4, seed=5):
+    r = synth.make_rng(seed)
+    fat = synth.fat_links(r, dims)
+    lng = synth.long_links(r, dims) if improved else None
+    op = oracle.Operator(dims, fat, lng, m)
+    B = synth.rhs(synth.make_rng(seed + 1), n, dims)
+    return op, B
+
+
+def test_thin_qr_matches_householder():
+    r = synth.make_rng(3)
+    M = synth.gaussian_complex(r, (300, 7))
+    Q, R = oracle.thin_qr(M)
+    q2, r2 = np.linalg.qr(M)
+    ph = np.diag(r2) / np.abs(np.diag(r2))
+    q2 = q2 * ph[None, :]
+    r2 = ph.conj()[:, None] * r2
+    assert np.abs(R - r2).max() <= 1e-12 * np.abs(r2).max()
+    assert np.abs(Q - q2).max() <= 1e-12
+    assert np.all(np.diag(R).real > 0) and np.abs(np.diag(R).imag).max() == 0
+    assert np.abs(np.tril(R, -1)).max() == 0
+
+
+def test_hpd_inverse():
+    r = synth.make_rng(4)
+    M = synth.gaussian_complex(r, (40, 9))
+    G = M.conj().T @ M
+    assert np.abs(oracle.hpd_inverse(G) @ G - np.eye(9)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("dims,improved,m,n", [((4, 4, 4, 4), False, 0.1, 4),
+                                               ((4, 4, 4, 4), True, 0.1, 5),
+                                               ((4, 4, 2, 6), True, 0.3, 1)])
+def test_block_cg_matches_dense_solve(dims, improved, m, n):
+    op, B = small_problem(dims, improved, m, n)
+    A = dense_A(op)
+    Xd = np.linalg.solve(A, oracle.to_mat(B))
+    X, info = oracle.block_cg_rq(op.apply, B, 1e-12)
+    assert info.converged and info.true_rel_res.max() <= 1e-12
+    Xm = oracle.to_mat(X)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(Xm - Xd) / np.linalg.norm(Xd) <= kappa * 1e-12
+    # true residual computed independently from the dense matrix
+    res = np.linalg.norm(oracle.to_mat(B) - A @ Xm, axis=0) / np.linalg.norm(oracle.to_mat(B), axis=0)
+    assert res.max() <= 1.01e-12
+
+
+def test_config1_block_cg():
+    fat, lng, B = synth.config_inputs(1)
+    op = oracle.Operator((4, 4, 4, 4), fat, lng, 0.1)
+    X, info = oracle.block_cg_rq(op.apply, B, 1e-10)
+    assert info.converged and info.true_rel_res.max() <= 1e-10
+    Xd = np.linalg.solve(dense_A(op), oracle.to_mat(B))
+    assert np.linalg.norm(oracle.to_mat(X) - Xd) / np.linalg.norm(Xd) <= 1e-7
+
+
+def test_n1_block_cg_is_cg():
+    op, B = small_problem(n=1, m=0.2)
+    tr = []
+    for k in (1, 2, 5, 12):
+        Xb, ib = oracle.block_cg_rq(op.apply, B, 1e-30, max_iter=k, trace=tr if k == 12 else None)
+        xc, ic = oracle.cg(op.apply, B[0], 1e-30, max_iter=k)
+        assert ib.iters == ic.iters == k
+        assert np.abs(Xb[0] - xc).max() <= 1e-10 * np.abs(xc).max()
+    # C_k = ||r_k|| (a positive real 1x1), S_{k+1} = ||r_{k+1}|| / ||r_k||
+    r = B[0].copy()
+    x = np.zeros_like(r)
+    p = r.copy()
+    rr = np.vdot(r, r).real
+    for k, rec in enumerate(tr[:8]):
+        assert abs(rec["C"][0, 0] - np.sqrt(rr)) <= 1e-10 * np.sqrt(rr)
+        Ap = op.apply(p[None])[0]
+        a = rr / np.vdot(p, Ap).real
+        x += a * p
+        r -= a * Ap
+        rr2 = np.vdot(r, r).real
+        assert abs(rec["S"][0, 0] - np.sqrt(rr2 / rr)) <= 1e-9 * np.sqrt(rr2 / rr)
+        p = r + (rr2 / rr) * p
+        rr = rr2
+
+
+def test_cg_matches_dense_solve():
+    op, B = small_problem(n=2, m=0.15)
+    A = dense_A(op)
+    for i in range(2):
+        x, info = oracle.cg(op.apply, B[i], 1e-12)
+        xd = np.linalg.solve(A, B[i].ravel())
+        assert info.converged and info.true_rel_res <= 1e-12
+        assert np.linalg.norm(x.ravel() - xd) / np.linalg.norm(xd) <= np.linalg.cond(A) * 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 4, 24])
+def test_free_field_finishes_in_five_iterations(n):
+    dims = (4, 4, 4, 4)
+    op = oracle.Operator(dims, synth.unit_links(dims), None, 0.1)
+    B = synth.rhs(synth.make_rng(9), n, dims)
+    X, info = oracle.block_cg_rq(op.apply, B, 1e-12)
+    assert info.converged and info.iters <= 5
+    x, ic = oracle.cg(op.apply, B[0], 1e-12)
+    assert ic.converged and ic.iters <= 5
+
+
+def test_blockcg_invariants():
+    op, B = small_problem(n=4, m=0.1, seed=17)
+    N = B.shape[0]
+    vh = B.shape[1]
+    A = lambda M: oracle.to_mat(op.apply(oracle.from_mat(M, vh)))
+    Bm = oracle.to_mat(B)
+    Q, C = oracle.thin_qr(Bm)
+    S = np.eye(N, dtype=complex)
+    P = np.zeros_like(Bm)
+    X = np.zeros_like(Bm)
+    Ps = []
+    eye = np.eye(N)
+    for k in range(10):
+        P = Q + P @ S.conj().T
+        assert np.abs(Q.conj().T @ P - eye).max() <= 1e-10          # Q_k^H P_k = I
+        assert np.abs(Q.conj().T @ Q - eye).max() <= 1e-10          # Q^H Q = I
+        AP = A(P)
+        for Pj in Ps:                                               # block A-conjugacy
+            assert np.abs(Pj.conj().T @ AP).max() <= 1e-9 * np.abs(P.conj().T @ AP).max()
+        Ps.append(P)
+        beta = oracle.hpd_inverse(P.conj().T @ AP)
+        X = X + P @ beta @ C
+        Qt = Q - AP @ beta
+        H = Qt.conj().T @ Qt
+        iter_norm = np.sqrt(np.real(np.diag(C.conj().T @ H @ C)))
+        true_norm = np.linalg.norm(Bm - A(X), axis=0)
+        assert np.abs(iter_norm - true_norm).max() <= 1e-9 * np.linalg.norm(Bm, axis=0).max()
+        S = oracle.cholesky_upper(H)
+        Q = np.linalg.solve(S.T, Qt.T).T
+        C = S @ C
+        # column norms of C are the residual norms (Sec. 6 identity, R = Q C)
+        assert np.abs(np.linalg.norm(C, axis=0) - true_norm).max() <= 1e-9 * np.linalg.norm(Bm, axis=0).max()
+
+
+def test_block_cg_function_follows_invariants_via_trace():
+    """The production oracle routine agrees with the step-by-step loop above."""
+    op, B = small_problem(n=4, m=0.1, seed=17)
+    tr = []
+    oracle.block_cg_rq(op.apply, B, 1e-30, max_iter=6, trace=tr)
+    Bm = oracle.to_mat(B)
+    _, C0 = oracle.thin_qr(Bm)
+    assert np.abs(tr[0]["C"] - C0).max() <= 1e-12 * np.abs(C0).max()
+    for a, b in zip(tr[:-1], tr[1:]):
+        assert np.abs(b["C"] - a["S"] @ a["C"]).max() <= 1e-12 * np.abs(b["C"]).max()
+
+
+def test_reliable_update_is_noop_in_fp64():
+    """In exact arithmetic a reliable update changes nothing (S^ = C^ C_k^{-1} = S_{k+1}).
+    In FP64 the iterated-residual trajectory must therefore match the plain solve
+    through several updates, until ordinary rounding drift separates them, and
+    both must reach the same solution."""
+    op, B = small_problem(n=4, m=0.4, seed=23)
+    tr = []
+    X0, i0 = oracle.block_cg_rq(op.apply, B, 1e-11)
+    X1, i1 = oracle.block_cg_rq(op.apply, B, 1e-11, ru_delta=0.1, trace=tr)
+    ru_at = [k for k, t in enumerate(tr) if t.get("ru")]
+    assert len(ru_at) >= 5
+    k3 = ru_at[2] + 2                        # through the first three updates
+    h0 = np.array(i0.history[:k3])
+    h1 = np.array(i1.history[:k3])
+    assert np.max(np.abs(h1 - h0) / h0) <= 1e-10
+    assert abs(i1.iters - i0.iters) <= max(1, i0.iters // 20)
+    assert np.abs(X1 - X0).max() <= 1e-9 * np.abs(X0).max()
+    assert i1.converged and i1.true_rel_res.max() <= 1e-11
+
+
+def test_reliable_update_wrong_c_old_would_fail():
+    """With S = C^ C_{k+1}^{-1} (the other reading of C_old) S becomes ~I and the
+    Krylov space is lost: the solve then stalls.  This keeps the C_k reading honest."""
+    op, B = small_problem(n=4, m=0.05, seed=23)
+    X0, i0 = oracle.block_cg_rq(op.apply, B, 1e-11)
+    tr = []
+    oracle.block_cg_rq(op.apply, B, 1e-11, ru_delta=0.1, trace=tr)
+    ru = [t for t in tr if t.get("ru")]
+    assert ru, "expected reliable updates"
+    for t in ru:
+        assert np.abs(t["S"] - np.eye(4)).max() > 1e-3
+
+
+def test_mixed_precision_emulation_reaches_tolerance():
+    op, B = small_problem(n=4, m=0.05, seed=29)
+    to32 = lambda a: a.astype(np.complex64).astype(np.complex128)
+    X, info = oracle.block_cg_rq(op.apply, B, 1e-10, ru_delta=0.1, sloppy=to32)
+    assert info.converged and info.true_rel_res.max() <= 1e-10
+    assert info.reliable_updates >= 3
+
+
+def test_breakdown_and_bad_input():
+    op, B = small_problem(n=3)
+    Bd = B.copy()
+    Bd[2] = Bd[0]
+    with pytest.raises(oracle.Breakdown):
+        oracle.block_cg_rq(op.apply, Bd, 1e-10)
+    Bz = B.copy()
+    Bz[1] = 0
+    with pytest.raises(ValueError):
+        oracle.block_cg_rq(op.apply, Bz, 1e-10)
+
+
+def test_solution_gauge_covariant():
+    from test_oracle_operator import gauge_rotate, parity_split
+    dims = (4, 4, 4, 6)
+    r = synth.make_rng(91)
+    fat = synth.fat_links(r, dims)
+    lng = synth.long_links(r, dims)
+    g = synth.gauge_transform(synth.make_rng(92), dims)
+    f2, l2 = gauge_rotate(dims, fat, lng, g)
+    op1 = oracle.Operator(dims, fat, lng, 0.2)
+    op2 = oracle.Operator(dims, f2, l2, 0.2)
+    even, _ = parity_split(dims)
+    B = synth.rhs(synth.make_rng(93), 3, dims)
+    gB = np.einsum("sab,nsb->nsa", g[even], B)
+    X1, _ = oracle.block_cg_rq(op1.apply, B, 1e-12)
+    X2, _ = oracle.block_cg_rq(op2.apply, gB, 1e-12)
+    gX1 = np.einsum("sab,nsb->nsa", g[even], X1)
+    assert np.abs(X2 - gX1).max() <= 1e-8 * np.abs(X1).max()
