@@ -1,0 +1,237 @@
+"""Benchmark: block CG (blockCGrQ) vs N independent CG solves on one MI355X.
+
+Workload (default): the 16^4 improved staggered operator (Gaussian fat links,
+Haar long links), m = 0.05, N = 16 Gaussian right-hand sides, FP64 storage,
+relative residual 1e-10 on every column.  One step is one complete block solve
+of the 16-column block (initial CholQR, all iterations, reliable updates and
+the final FP64 true-residual check), with inputs already resident in HBM.
+
+Printed: ONE JSON line with the metric (solve time per right-hand side, lower
+is better), the CG-baseline time per right-hand side on the same operator and
+tolerance, the roofline of the dominant kernel (algorithmic bytes over its
+average launch time measured with HIP events on the solver's stream), and the
+CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solve time per RHS (block CG vs N× CG) at fixed residual; Dslash GB/s % HBM"
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_1710_09745_amd", "csrc")
+
+# Algorithmic bytes per even (or odd) site of one launch, FP64 storage (s = 8 bytes
+# per real), N right-hand sides: each link and each vector moved once.
+#   hop_oe : 16 folded links (288 reals) + read P, write T (12 N reals)
+#   hop_eo : 16 folded links + read T, read P (mass term), write AP (18 N reals)
+#   gram   : read both block vectors (12 N reals), or one when they alias
+#   pass_a : read Q, AP, write Q (18 N reals)
+#   pass_b : read Qt, P, X, write Q, P, X (36 N reals)
+def model_bytes_per_site(kernel, N, s=8, s_link=8, nl=16, aliased_gram=None):
+    link = nl * 18 * s_link
+    if kernel == "hop_oe":
+        return link + 12 * N * s
+    if kernel == "hop_eo":
+        return link + 18 * N * s
+    if kernel == "gram":
+        return 6 * N * s if aliased_gram else 12 * N * s
+    if kernel == "pass_a":
+        return 18 * N * s
+    if kernel == "pass_b":
+        return 24 * N * s + 12 * N * 8
+    return None
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload_key, launch_bytes):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries (FETCH_SIZE and
+    WRITE_SIZE in KiB per dispatch, scaled by the copy-kernel calibration), or None
+    when absent or taken on a different kernel source."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload_key}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return float(d["hbm_bytes_per_launch"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cg-steps", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU; the multi-GPU path (right-hand-side blocks "
+              "per GPU, or lattice domain decomposition) is a design only. Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1710_09745_amd import bcg, synth
+
+    c = synth.CONFIGS[2]
+    dims, m, N, tol = c["dims"], c["mass"], c["nrhs"], c["tol"]
+    workload = "16^4 improved staggered (fat N(0,1)/3 + Haar long), m=0.05, N=16, FP64, tol 1e-10"
+    wkey = "config2"
+    fat, lng, B = synth.config_inputs(2)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = bcg.Context(dims, improved=True, device=dev)
+    ctx.load_links(fat, lng)
+    ctx.set_mass(m)
+    ctx.set_solver(tol=tol, max_iter=100000, prec="fp64", ru_delta=0.1)
+    Bt = torch.from_numpy(B).to(dev)
+    torch.cuda.synchronize()
+    print(f"[bench] workload: {workload}", file=sys.stderr, flush=True)
+
+    # warmup, with every kernel class timed to find the dominant one
+    ctx.set_profiling(bcg.KERNELS)
+    ctx.profile_reset()
+    info = None
+    for _ in range(max(1, args.warmup)):
+        X, info = ctx.solve(Bt)
+    torch.cuda.synchronize()
+    breakdown = {}
+    for k in bcg.KERNELS:
+        n, ms = ctx.kernel_time(k)
+        if n:
+            breakdown[k] = {"launches": n, "total_ms": ms}
+    dominant = max((k for k in breakdown if model_bytes_per_site(k, N) is not None),
+                   key=lambda k: breakdown[k]["total_ms"])
+    print(f"[bench] warmup solve: iters={info['iters']} rus={info['reliable_updates']} "
+          f"max true rel res={info['max_true_rel_res']:.2e}; dominant kernel {dominant}",
+          file=sys.stderr, flush=True)
+
+    # timed region: K block solves; only the dominant kernel is bracketed by events
+    ctx.set_profiling([dominant])
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for _ in range(args.steps):
+        X, info = ctx.solve(Bt)
+        iters.append(info["iters"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    launches, kms = ctx.kernel_time(dominant)
+    ctx.set_profiling([])
+    max_res = info["max_true_rel_res"]
+
+    # CG baseline: N independent solves, same operator and tolerance
+    Xc, ic = ctx.solve_cg(Bt)      # warm
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.cg_steps):
+        Xc, ic = ctx.solve_cg(Bt)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    cg_ms = (t3 - t2) * 1e3 / args.cg_steps
+    print(f"[bench] block {ms_per_step:.2f} ms/solve ({iters[-1]} iters), CG {cg_ms:.2f} ms "
+          f"for {N} columns ({ic['iters']} iters)", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel
+    Vh = synth.volume(dims) // 2
+    per_site = model_bytes_per_site(dominant, N, aliased_gram=None)
+    launch_bytes = per_site * Vh
+    avg_ms = kms / max(launches, 1)
+    achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = load_traffic(dominant, wkey, launch_bytes)
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "bytes_per_launch": launch_bytes,
+                "avg_launch_ms": round(avg_ms, 5), "launches": launches}
+    dslash = {}
+    for k in ("hop_oe", "hop_eo"):
+        if k in breakdown:
+            b = model_bytes_per_site(k, N) * Vh
+            t = breakdown[k]["total_ms"] / breakdown[k]["launches"]
+            dslash[k] = {"GB/s": round(b / (t * 1e-3) / 1e9, 1),
+                         "frac_hbm": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(dims, fat, lng, m, B, tol, iters[-1], args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms_per_step / N, 4),
+        "unit": "ms/RHS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "lattice": list(dims), "nrhs": N, "mass": m,
+                   "tol": tol, "storage": "fp64", "parallelism": "single GPU"},
+        "block_iters": iters[-1],
+        "block_reliable_updates": info["reliable_updates"],
+        "block_max_true_rel_res": max_res,
+        "cg_ms_per_rhs": round(cg_ms / N, 4),
+        "cg_iters_per_rhs": round(ic["iters"] / N, 1),
+        "speedup_vs_cg": round(cg_ms / ms_per_step, 3),
+        "roofline": roofline,
+        "dslash": dslash,
+        "kernel_breakdown_warmup_ms": {k: round(v["total_ms"], 3) for k, v in breakdown.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def cpu_baseline(dims, fat, lng, m, B, tol, gpu_iters, budget_s):
+    """The oracle's blockCGrQ on the same input, run for a bounded number of
+    iterations and extrapolated to the GPU's iteration count."""
+    import oracle
+
+    op = oracle.Operator(dims, fat, lng, m)
+    t0 = time.perf_counter()
+    op.apply(B)
+    t_apply = time.perf_counter() - t0
+    k = max(2, min(gpu_iters, int(budget_s / max(t_apply * 1.3, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.block_cg_rq(op.apply, B, 1e-30, max_iter=k)
+    t = time.perf_counter() - t0
+    per_iter = t / k
+    N = B.shape[0]
+    est = per_iter * gpu_iters
+    return {"value": round(est * 1e3 / N, 2), "unit": "ms/RHS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"oracle blockCGrQ (C stencil + NumPy) on the same 16^4 N=16 input, first {k} "
+                      f"iterations in {t:.1f} s, extrapolated to the GPU's {gpu_iters} iterations"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * bcg.h -- C ABI of the MI355X (gfx950) block conjugate-gradient library.
+ *
+ * The library solves A X = B for a block of N right-hand sides at once with
+ * blockCGrQ: the block CG of O'Leary retooled by Dubrulle so that the residual
+ * block is re-orthonormalised every iteration by a thin QR (Sec. 4, Alg. 1),
+ * where the thin QR is CholQR (Sec. 6, Alg. 2) and, in mixed precision,
+ * the residual is periodically replaced by the true one with the block
+ * reliable update (Sec. 6, Alg. 3).
+ *
+ * Operator.  The improved staggered stencil of Sec. 3.2 (Eq. 2) with fat
+ * (one-hop) links F and long (three-hop) links G, read with the standard
+ * staggered phases and an anti-Hermitian hopping term:
+ *   (D psi)(x) = sum_mu eta_mu(x) [ F_mu(x) psi(x+mu) - F_mu(x-mu)^H psi(x-mu)
+ *                                 + G_mu(x) psi(x+3mu) - G_mu(x-3mu)^H psi(x-3mu) ]
+ *   eta_0 = 1, eta_1 = (-1)^x0, eta_2 = (-1)^(x0+x1), eta_3 = (-1)^(x0+x1+x2),
+ * periodic in all four directions.  The naive operator drops the G terms.
+ * The solver inverts the even-even Schur block of the normal operator
+ * (Sec. 3.2):
+ *   A = 4 m^2 - D_eo D_oe      (Hermitian positive definite, lambda_min >= 4 m^2)
+ *
+ * Layouts (all complex128, C order, interleaved re/im):
+ *   dims    = {Lx, Ly, Lz, Lt}, every extent even and >= 2, V = Lx Ly Lz Lt.
+ *   lex(x)  = x0 + Lx*(x1 + Ly*(x2 + Lz*x3)); parity(x) = (x0+x1+x2+x3) mod 2.
+ *   links   [4][V][3][3]: U_mu(x) at [mu][lex(x)], (U v)_a = sum_b U_ab v_b.
+ *   vectors [nrhs][V/2][3]: nrhs colour-vector fields on one checkerboard,
+ *           site index cb = lex(x) >> 1 (x0 is the fastest coordinate, so the
+ *           even and odd sites each map one-to-one onto 0 .. V/2-1).
+ *
+ * Memory.  Vector and gradient arguments are DEVICE pointers owned by the
+ * caller (e.g. the data of a torch tensor); the library never frees or keeps
+ * them.  Links are copied into library-owned device storage by
+ * bcg_load_links (from host or device memory).  Work buffers are allocated
+ * by the library on first use for a given nrhs and precision and kept until
+ * bcg_destroy.
+ *
+ * Streams.  Every kernel is launched on the context's stream (given to
+ * bcg_create; NULL = the null stream).  bcg_apply, bcg_hop and
+ * bcg_link_force only enqueue work (stream-ordered, asynchronous to the
+ * host).  bcg_solve and bcg_solve_cg read convergence information and return
+ * after the solve has completed on the stream.
+ *
+ * Errors.  Every function returns a bcg_status; nothing throws or aborts
+ * across the ABI.  bcg_last_error gives a message for the last failure on a
+ * context.  A context is not thread-safe: use one per host thread.
+ */
+#ifndef BCG_H
+#define BCG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bcg_ctx bcg_ctx;
+
+typedef enum {
+    BCG_OK = 0,
+    BCG_ERR_ARG = -1,            /* bad argument: null pointer, bad dims, nrhs out of range,
+                                    zero right-hand-side column, unknown precision */
+    BCG_ERR_HIP = -2,            /* a HIP runtime call failed */
+    BCG_ERR_NOMEM = -3,          /* device or pinned host allocation failed */
+    BCG_ERR_NOT_CONVERGED = -4,  /* max_iter reached; X holds the current iterate */
+    BCG_ERR_BREAKDOWN = -5,      /* a Cholesky factor met a non-positive pivot before
+                                    convergence (R^H R singular, Sec. 4); X holds the
+                                    current iterate */
+    BCG_ERR_STATE = -6           /* call out of order, e.g. solve before bcg_load_links */
+} bcg_status;
+
+/* Storage precision of the low-precision ("sloppy") block vectors and links.
+ * Y (solution), X (update since the last reliable update), B, the true
+ * residual, every N x N matrix and the Gram accumulation stay FP64. */
+typedef enum {
+    BCG_PREC_FP64 = 0,
+    BCG_PREC_FP32 = 1,
+    BCG_PREC_FP16 = 2,           /* FP16 components with one FP32 scale per site and column */
+    BCG_PREC_BF16 = 3            /* BF16 components with one FP32 scale per site and column */
+} bcg_prec;
+
+#define BCG_MAX_RHS 64           /* N <= 64 (Sec. 6: small N x N matrices) */
+
+typedef struct {
+    int iters;                   /* block iterations (solve) or summed CG iterations (solve_cg) */
+    int reliable_updates;        /* reliable updates performed (Alg. 3) */
+    int status;                  /* bcg_status of the solve */
+    int restarts;                /* solve_cg: true-residual restarts; solve: unused (0) */
+    double seconds;              /* wall time of the solve on the host */
+    double max_true_rel_res;     /* max_i ||b_i - A x_i|| / ||b_i||, FP64 operator */
+    double *true_rel_res;        /* optional caller array [nrhs] (host) or NULL */
+} bcg_stats;
+
+/* Create a context for one lattice.  dims: four even extents >= 2.
+ * improved: 0 = naive operator (fat links only), 1 = fat + long links.
+ * hip_stream: a hipStream_t (NULL = null stream).  *out receives the context. */
+int bcg_create(bcg_ctx **out, const int dims[4], int improved, void *hip_stream);
+
+/* Free every device, pinned and host allocation owned by the context. */
+int bcg_destroy(bcg_ctx *ctx);
+
+/* Load links in the canonical layout [4][V][3][3] complex128.  fat is
+ * required; lng must be non-NULL iff the context is improved.  on_device:
+ * 0 = host pointers, 1 = device pointers.  The data is copied; the staggered
+ * phases and the hop signs are folded into library-owned copies for each
+ * output parity and each storage precision.  Synchronous w.r.t. the inputs
+ * (they may be freed on return). */
+int bcg_load_links(bcg_ctx *ctx, const void *fat, const void *lng, int on_device);
+
+/* Set the mass m of A = 4 m^2 - D_eo D_oe (any real m; m = 0 gives the
+ * positive semi-definite -D_eo D_oe). */
+int bcg_set_mass(bcg_ctx *ctx, double m);
+
+/* Solver parameters.  tol > 0: stop when every column's relative residual
+ * ||b_i - A x_i|| / ||b_i|| <= tol, tested on the iterated residual and then
+ * confirmed with the FP64 true residual (a reliable update and further
+ * iterations follow if a column misses).  max_iter >= 1.  sloppy_prec: a
+ * bcg_prec.  ru_delta in [0, 1): reliable update when the maximum relative
+ * iterated residual has dropped by this factor since the last one (0 = only
+ * at exit; Sec. 7.1 uses 0.1). */
+int bcg_set_solver(bcg_ctx *ctx, double tol, int max_iter, int sloppy_prec, double ru_delta);
+
+/* out = A in for nrhs even fields (FP64 links, FP64 arithmetic).
+ * in, out: device [nrhs][V/2][3] complex128, must not overlap. */
+int bcg_apply(bcg_ctx *ctx, const void *in, void *out, int nrhs);
+
+/* One checkerboard hop out = D_{p,1-p} in (p = out_parity: 1 gives D_oe,
+ * 0 gives D_eo), FP64.  in: fields on parity 1-p, out: on parity p, both
+ * device [nrhs][V/2][3] complex128, must not overlap. */
+int bcg_hop(bcg_ctx *ctx, int out_parity, const void *in, void *out, int nrhs);
+
+/* Solve A X = B with blockCGrQ (Alg. 1-3) for nrhs columns at once.
+ * B, X: device [nrhs][V/2][3] complex128, must not overlap.  use_guess:
+ * 1 = X holds the initial guess X0, 0 = start from X0 = 0.  stats may be
+ * NULL.  Returns BCG_OK, BCG_ERR_NOT_CONVERGED or BCG_ERR_BREAKDOWN (X holds
+ * the current iterate in both), or an argument / runtime error. */
+int bcg_solve(bcg_ctx *ctx, const void *B, void *X, int nrhs, int use_guess, bcg_stats *stats);
+
+/* The baseline: nrhs independent single right-hand-side CG solves, one after
+ * the other (Sec. 7.1), on the same operator, tolerance and precision
+ * (FP64 storage only).  Same arguments and returns as bcg_solve with X0 = 0. */
+int bcg_solve_cg(bcg_ctx *ctx, const void *B, void *X, int nrhs, bcg_stats *stats);
+
+/* Link force: the gradients w.r.t. the fat and long links of a loss L with
+ * dL = -Re sum_i Lam_i^H dA X_i (X = A^{-1} B, Lam = A^{-1} dL/dX), in the
+ * complex convention grad = dL/dRe + i dL/dIm and without projection:
+ *   with Y_X = D_oe X, Y_L = D_oe Lam and, for a link W_mu(x) of hop length
+ *   k (1 fat, 3 long), y = x + k mu:
+ *   x even: grad W_mu(x) = +eta_mu(x) sum_i [ Lam_i(x) Y_X,i(y)^H + X_i(x) Y_L,i(y)^H ]
+ *   x odd : grad W_mu(x) = -eta_mu(x) sum_i [ Y_X,i(x) Lam_i(y)^H + Y_L,i(x) X_i(y)^H ]
+ * X, Lam: device [nrhs][V/2][3] even fields; grad_fat, grad_long: device
+ * [4][V][3][3] complex128, overwritten (grad_long ignored and may be NULL for
+ * the naive operator).  Stream-ordered. */
+int bcg_link_force(bcg_ctx *ctx, const void *X, const void *Lam, int nrhs, void *grad_fat,
+                   void *grad_long);
+
+/* Per-kernel timing with HIP events on the context's stream.  mask: bit set of
+ * BCG_K_* kernels to time (0 = off).  While on, each launch of a selected
+ * kernel is bracketed by two events; bcg_kernel_time returns the number of
+ * timed launches and their summed duration in milliseconds since the last
+ * bcg_profile_reset, after synchronising the stream. */
+enum {
+    BCG_K_HOP_OE = 0, BCG_K_HOP_EO = 1, BCG_K_GRAM = 2, BCG_K_REDUCE = 3, BCG_K_SMALL = 4,
+    BCG_K_PASS_A = 5, BCG_K_PASS_B = 6, BCG_K_CG_VEC = 7, BCG_K_CONVERT = 8, BCG_K_OTHER = 9,
+    BCG_K_COUNT = 10
+};
+int bcg_set_profiling(bcg_ctx *ctx, unsigned mask);
+int bcg_profile_reset(bcg_ctx *ctx);
+int bcg_kernel_time(bcg_ctx *ctx, int kernel, long *launches, double *total_ms);
+
+/* Message for the last error on ctx (static storage owned by the context;
+ * valid until the next call on it).  ctx may be NULL for creation errors. */
+const char *bcg_last_error(const bcg_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BCG_H */

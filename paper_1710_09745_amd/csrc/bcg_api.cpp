@@ -1,0 +1,839 @@
+// C ABI of the block CG library: context, link loading, work buffers, the
+// blockCGrQ driver loop (Alg. 1-3), the single right-hand-side CG baseline,
+// the operator applications and the link force.
+//
+// The driver enqueues whole iterations without waiting: every iteration kernel
+// first reads the device SolveState and does nothing once a single-workgroup
+// N x N kernel has raised `halt` (convergence, a reliable-update trigger or a
+// breakdown).  The host reads the state (one small device-to-host copy into
+// pinned memory) only between chunks of iterations, sized from the observed
+// convergence rate, and then carries out the reliable update (Alg. 3) or the
+// final true-residual check.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bcg.h"
+#include "internal.h"
+
+using namespace bcg;
+
+namespace {
+
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct ProfEvent {
+    int kid;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct bcg_ctx {
+    Geom g{};
+    int dims[4]{};
+    int improved = 0;
+    int nl = 8;
+    long V = 0, Vh = 0;
+    hipStream_t stream = nullptr;
+    double mass = 0.0;
+    double tol = 1e-10;
+    int max_iter = 100000;
+    Prec sloppy = Prec::FP64;
+    double ru_delta = 0.1;
+    bool links = false;
+    void* W64[2] = {nullptr, nullptr};
+    void* Wsl[2] = {nullptr, nullptr};
+    Prec wsl_prec = Prec::FP64;
+    // device state
+    SolveState* d_state = nullptr;
+    SolveState* h_state = nullptr;  // pinned
+    CgState* d_cg = nullptr;
+    CgState* h_cg = nullptr;        // pinned
+    double2* mats = nullptr;        // small matrices, 10 x [64][64]
+    double2* partials = nullptr;    // GRAM_BLOCKS x 64 x 64
+    double* nparts = nullptr;       // NORM_BLOCKS x 64 norm partials, then the CG dot partials
+    long dot_off = 0;               // offset of the CG dot partials in nparts
+    double* d_vec = nullptr;        // bnorm[64], true_relres[64]
+    int* d_flags = nullptr;         // ru_skip
+    double* h_vec = nullptr;        // pinned [128]
+    Buf work[16];
+    std::string err;
+    // profiling
+    unsigned prof_mask = 0;
+    std::vector<ProfEvent> pending;
+    std::vector<hipEvent_t> pool;
+    long prof_n[BCG_K_COUNT]{};
+    double prof_ms[BCG_K_COUNT]{};
+};
+
+namespace {
+
+// work buffer slots
+enum { WB_B64, WB_Y, WB_X, WB_R64, WB_T64, WB_P0, WB_P1, WB_Q0, WB_Q1, WB_AP, WB_T, WB_A0, WB_A1, WB_A2, WB_A3 };
+// small matrix slots
+enum { M_G, M_H, M_BETA, M_BETAC, M_C, M_CINV, M_SINV, M_SH, M_HR, M_ID, M_COUNT };
+
+thread_local std::string g_create_err;
+
+int fail(bcg_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_create_err = msg;
+    return code;
+}
+
+#define HIPCK(call)                                                                              \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(ctx, BCG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+#define RETCK(call)                      \
+    do {                                 \
+        int r_ = (call);                 \
+        if (r_ != BCG_OK) return r_;     \
+    } while (0)
+
+size_t prec_bytes(Prec p) {
+    switch (p) {
+        case Prec::FP64: return 16;
+        case Prec::FP32: return 8;
+        default: return 4;
+    }
+}
+
+int ensure(bcg_ctx* ctx, int slot, size_t bytes) {
+    Buf& b = ctx->work[slot];
+    if (b.bytes >= bytes) return BCG_OK;
+    if (b.p) {
+        HIPCK(hipStreamSynchronize(ctx->stream));
+        HIPCK(hipFree(b.p));
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        b.p = nullptr;
+        return fail(ctx, BCG_ERR_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    b.bytes = bytes;
+    return BCG_OK;
+}
+
+void* W(bcg_ctx* ctx, int slot) { return ctx->work[slot].p; }
+double2* Wd(bcg_ctx* ctx, int slot) { return (double2*)ctx->work[slot].p; }
+double2* M(bcg_ctx* ctx, int m) { return ctx->mats + (size_t)m * MAXN * MAXN; }
+
+// ---- profiling -----------------------------------------------------------------------------
+hipEvent_t prof_event(bcg_ctx* ctx) {
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Prof {
+    bcg_ctx* ctx;
+    int kid;
+    hipEvent_t a = nullptr;
+    Prof(bcg_ctx* c, int k) : ctx(c), kid(k) {
+        if (ctx->prof_mask & (1u << kid)) {
+            a = prof_event(ctx);
+            if (a) (void)hipEventRecord(a, ctx->stream);
+        }
+    }
+    ~Prof() {
+        if (a) {
+            hipEvent_t b = prof_event(ctx);
+            if (b) {
+                (void)hipEventRecord(b, ctx->stream);
+                ctx->pending.push_back(ProfEvent{kid, a, b});
+            } else {
+                ctx->pool.push_back(a);
+            }
+        }
+    }
+};
+
+void prof_collect(bcg_ctx* ctx) {
+    for (auto& pe : ctx->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+            ctx->prof_n[pe.kid] += 1;
+            ctx->prof_ms[pe.kid] += ms;
+        }
+        ctx->pool.push_back(pe.a);
+        ctx->pool.push_back(pe.b);
+    }
+    ctx->pending.clear();
+}
+
+int sync(bcg_ctx* ctx) {
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    if (!ctx->pending.empty()) prof_collect(ctx);
+    return BCG_OK;
+}
+
+// ---- argument checks -----------------------------------------------------------------------
+int check_nrhs(bcg_ctx* ctx, int nrhs) {
+    if (nrhs < 1 || nrhs > BCG_MAX_RHS)
+        return fail(ctx, BCG_ERR_ARG, "nrhs must be in [1, 64], got " + std::to_string(nrhs));
+    return BCG_OK;
+}
+
+int check_ready(bcg_ctx* ctx) {
+    if (!ctx->links) return fail(ctx, BCG_ERR_STATE, "links not loaded (call bcg_load_links first)");
+    return BCG_OK;
+}
+
+// ---- building blocks -----------------------------------------------------------------------
+long nvec(bcg_ctx* ctx, int N) { return (long)N * 3 * ctx->Vh; }
+
+int hop(bcg_ctx* ctx, Prec p, int out_parity, const void* in, void* out, const void* ctr, int N,
+        int epi, const int* halt, double* dot = nullptr) {
+    const void* Wp = (p == Prec::FP64) ? ctx->W64[out_parity] : ctx->Wsl[out_parity];
+    HopShape h = hop_shape(N);
+    Prof pr(ctx, out_parity == 1 ? BCG_K_HOP_OE : BCG_K_HOP_EO);
+    HIPCK(launch_hop(p, ctx->nl, Wp, in, out, ctr, 4.0 * ctx->mass * ctx->mass, N, ctx->g,
+                     out_parity, epi, h, halt, dot, ctx->stream));
+    return BCG_OK;
+}
+
+// out = A in, FP64, internal layout; tmp: odd-parity scratch
+int apply64(bcg_ctx* ctx, const void* in, void* out, void* tmp, int N, const int* halt) {
+    RETCK(hop(ctx, Prec::FP64, 1, in, tmp, nullptr, N, EPI_PLAIN_, halt));
+    RETCK(hop(ctx, Prec::FP64, 0, tmp, out, in, N, EPI_MASS_, halt));
+    return BCG_OK;
+}
+
+int gram(bcg_ctx* ctx, Prec p, const void* A, const void* B, int N, double2* out, const int* halt) {
+    {
+        Prof pr(ctx, BCG_K_GRAM);
+        HIPCK(launch_gram(p, A, B, N, (int)ctx->Vh, ctx->partials, halt, ctx->stream));
+    }
+    Prof pr(ctx, BCG_K_REDUCE);
+    HIPCK(launch_gram_reduce(ctx->partials, N, (int)ctx->Vh, out, halt, ctx->stream));
+    return BCG_OK;
+}
+
+int colnorms(bcg_ctx* ctx, const double2* V, int N, double* out) {
+    Prof pr(ctx, BCG_K_OTHER);
+    HIPCK(launch_colnorm2(V, N, (int)ctx->Vh, ctx->nparts, ctx->stream));
+    HIPCK(launch_colnorm_reduce(ctx->nparts, N, (int)ctx->Vh, out, 1, ctx->stream));
+    return BCG_OK;
+}
+
+int read_state(bcg_ctx* ctx) {
+    HIPCK(hipMemcpyAsync(ctx->h_state, ctx->d_state, sizeof(SolveState), hipMemcpyDeviceToHost,
+                         ctx->stream));
+    return sync(ctx);
+}
+
+int alloc_solve(bcg_ctx* ctx, int N, Prec ps) {
+    const size_t n64 = (size_t)nvec(ctx, N) * 16, nsl = (size_t)nvec(ctx, N) * prec_bytes(ps);
+    for (int s : {WB_B64, WB_Y, WB_X, WB_R64, WB_T64}) RETCK(ensure(ctx, s, n64));
+    for (int s : {WB_P0, WB_P1, WB_Q0, WB_Q1, WB_AP, WB_T}) RETCK(ensure(ctx, s, nsl));
+    return BCG_OK;
+}
+
+int ensure_sloppy_links(bcg_ctx* ctx, Prec ps) {
+    if (ps == Prec::FP64) return BCG_OK;
+    if (ps != Prec::FP32) return fail(ctx, BCG_ERR_ARG, "16-bit storage is not available in this build");
+    if (ctx->Wsl[0] && ctx->wsl_prec == ps) return BCG_OK;
+    const long n = (long)ctx->nl * 9 * ctx->Vh;
+    for (int p = 0; p < 2; ++p) {
+        if (!ctx->Wsl[p]) {
+            if (hipMalloc(&ctx->Wsl[p], (size_t)n * prec_bytes(ps)) != hipSuccess)
+                return fail(ctx, BCG_ERR_NOMEM, "sloppy link allocation failed");
+        }
+        Prof pr(ctx, BCG_K_CONVERT);
+        HIPCK(launch_convert(Prec::FP64, ctx->W64[p], ps, ctx->Wsl[p], n, ctx->stream));
+    }
+    ctx->wsl_prec = ps;
+    return BCG_OK;
+}
+
+void fill_stats(bcg_stats* st, int iters, int rus, int status, int restarts, double secs,
+                const double* tr, int N) {
+    if (!st) return;
+    st->iters = iters;
+    st->reliable_updates = rus;
+    st->status = status;
+    st->restarts = restarts;
+    st->seconds = secs;
+    double mx = 0.0;
+    for (int i = 0; i < N; ++i) mx = std::fmax(mx, tr[i]);
+    st->max_true_rel_res = mx;
+    if (st->true_rel_res)
+        for (int i = 0; i < N; ++i) st->true_rel_res[i] = tr[i];
+}
+
+}  // namespace
+
+// =============================================================================================
+extern "C" {
+
+int bcg_create(bcg_ctx** out, const int dims[4], int improved, void* hip_stream) {
+    bcg_ctx* ctx = nullptr;
+    if (!out || !dims) return fail(nullptr, BCG_ERR_ARG, "null argument");
+    *out = nullptr;
+    long V = 1;
+    for (int d = 0; d < 4; ++d) {
+        if (dims[d] < 2 || dims[d] % 2)
+            return fail(nullptr, BCG_ERR_ARG, "every lattice extent must be even and >= 2");
+        V *= dims[d];
+    }
+    if (V >= (1L << 30)) return fail(nullptr, BCG_ERR_ARG, "lattice too large for 32-bit site indices");
+    if (improved != 0 && improved != 1) return fail(nullptr, BCG_ERR_ARG, "improved must be 0 or 1");
+    static bool setup = false;
+    if (!setup) {
+        hipError_t e = small_setup();
+        if (e != hipSuccess) return fail(nullptr, BCG_ERR_HIP, std::string("kernel setup: ") + hipGetErrorString(e));
+        setup = true;
+    }
+    ctx = new bcg_ctx();
+    for (int d = 0; d < 4; ++d) {
+        ctx->dims[d] = dims[d];
+        ctx->g.L[d] = dims[d];
+    }
+    ctx->V = V;
+    ctx->Vh = V / 2;
+    ctx->g.Vh = (int)ctx->Vh;
+    ctx->improved = improved;
+    ctx->nl = improved ? 16 : 8;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->dot_off = (long)NORM_BLOCKS * MAXN;
+    bool ok = hipMalloc(&ctx->d_state, sizeof(SolveState)) == hipSuccess &&
+              hipHostMalloc(&ctx->h_state, sizeof(SolveState)) == hipSuccess &&
+              hipMalloc(&ctx->d_cg, sizeof(CgState)) == hipSuccess &&
+              hipHostMalloc(&ctx->h_cg, sizeof(CgState)) == hipSuccess &&
+              hipMalloc(&ctx->mats, sizeof(double2) * M_COUNT * MAXN * MAXN) == hipSuccess &&
+              hipMalloc(&ctx->partials, sizeof(double2) * GRAM_BLOCKS * MAXN * MAXN) == hipSuccess &&
+              hipMalloc(&ctx->nparts, sizeof(double) * ((long)NORM_BLOCKS * MAXN + ctx->Vh / 256 + 1)) == hipSuccess &&
+              hipMalloc(&ctx->d_vec, sizeof(double) * 4 * MAXN) == hipSuccess &&
+              hipMalloc(&ctx->d_flags, sizeof(int) * 16) == hipSuccess &&
+              hipHostMalloc(&ctx->h_vec, sizeof(double) * 4 * MAXN) == hipSuccess;
+    if (!ok) {
+        bcg_destroy(ctx);
+        return fail(nullptr, BCG_ERR_NOMEM, "context allocation failed");
+    }
+    *out = ctx;
+    return BCG_OK;
+}
+
+int bcg_destroy(bcg_ctx* ctx) {
+    if (!ctx) return BCG_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    prof_collect(ctx);
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    for (auto& b : ctx->work)
+        if (b.p) (void)hipFree(b.p);
+    for (int p = 0; p < 2; ++p) {
+        if (ctx->W64[p]) (void)hipFree(ctx->W64[p]);
+        if (ctx->Wsl[p]) (void)hipFree(ctx->Wsl[p]);
+    }
+    if (ctx->d_state) (void)hipFree(ctx->d_state);
+    if (ctx->h_state) (void)hipHostFree(ctx->h_state);
+    if (ctx->d_cg) (void)hipFree(ctx->d_cg);
+    if (ctx->h_cg) (void)hipHostFree(ctx->h_cg);
+    if (ctx->mats) (void)hipFree(ctx->mats);
+    if (ctx->partials) (void)hipFree(ctx->partials);
+    if (ctx->nparts) (void)hipFree(ctx->nparts);
+    if (ctx->d_vec) (void)hipFree(ctx->d_vec);
+    if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+    if (ctx->h_vec) (void)hipHostFree(ctx->h_vec);
+    delete ctx;
+    return BCG_OK;
+}
+
+int bcg_load_links(bcg_ctx* ctx, const void* fat, const void* lng, int on_device) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (!fat) return fail(ctx, BCG_ERR_ARG, "fat links are required");
+    if ((lng != nullptr) != (ctx->improved != 0))
+        return fail(ctx, BCG_ERR_ARG, "long links must be given iff the context is improved");
+    const size_t bytes = (size_t)4 * ctx->V * 9 * 16;
+    const void* dfat = fat;
+    const void* dlng = lng;
+    void* tmp = nullptr;
+    if (!on_device) {
+        const size_t tot = bytes * (ctx->improved ? 2 : 1);
+        if (hipMalloc(&tmp, tot) != hipSuccess) return fail(ctx, BCG_ERR_NOMEM, "link staging allocation failed");
+        HIPCK(hipMemcpyAsync(tmp, fat, bytes, hipMemcpyHostToDevice, ctx->stream));
+        dfat = tmp;
+        if (ctx->improved) {
+            HIPCK(hipMemcpyAsync((char*)tmp + bytes, lng, bytes, hipMemcpyHostToDevice, ctx->stream));
+            dlng = (char*)tmp + bytes;
+        }
+    }
+    const size_t wbytes = (size_t)ctx->nl * 9 * ctx->Vh * 16;
+    for (int p = 0; p < 2; ++p) {
+        if (!ctx->W64[p] && hipMalloc(&ctx->W64[p], wbytes) != hipSuccess) {
+            if (tmp) (void)hipFree(tmp);
+            return fail(ctx, BCG_ERR_NOMEM, "link allocation failed");
+        }
+        HIPCK(pack_links(Prec::FP64, dfat, dlng, ctx->W64[p], ctx->g, p, ctx->nl, ctx->stream));
+    }
+    ctx->wsl_prec = Prec::FP64;   // sloppy copies are rebuilt from the new links on demand
+    if (ctx->Wsl[0]) {
+        (void)hipFree(ctx->Wsl[0]);
+        (void)hipFree(ctx->Wsl[1]);
+        ctx->Wsl[0] = ctx->Wsl[1] = nullptr;
+    }
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    if (tmp) (void)hipFree(tmp);
+    ctx->links = true;
+    return BCG_OK;
+}
+
+int bcg_set_mass(bcg_ctx* ctx, double m) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (!std::isfinite(m)) return fail(ctx, BCG_ERR_ARG, "mass must be finite");
+    ctx->mass = m;
+    return BCG_OK;
+}
+
+int bcg_set_solver(bcg_ctx* ctx, double tol, int max_iter, int sloppy_prec, double ru_delta) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (!(tol > 0.0) || !(tol < 1.0)) return fail(ctx, BCG_ERR_ARG, "tol must be in (0, 1)");
+    if (max_iter < 1) return fail(ctx, BCG_ERR_ARG, "max_iter must be >= 1");
+    if (sloppy_prec < 0 || sloppy_prec > 3) return fail(ctx, BCG_ERR_ARG, "unknown precision");
+    if (!(ru_delta >= 0.0) || !(ru_delta < 1.0)) return fail(ctx, BCG_ERR_ARG, "ru_delta must be in [0, 1)");
+    ctx->tol = tol;
+    ctx->max_iter = max_iter;
+    ctx->sloppy = (Prec)sloppy_prec;
+    ctx->ru_delta = ru_delta;
+    return BCG_OK;
+}
+
+int bcg_apply(bcg_ctx* ctx, const void* in, void* out, int nrhs) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (!in || !out) return fail(ctx, BCG_ERR_ARG, "null vector pointer");
+    RETCK(check_nrhs(ctx, nrhs));
+    RETCK(check_ready(ctx));
+    const size_t b = (size_t)nvec(ctx, nrhs) * 16;
+    RETCK(ensure(ctx, WB_A0, b));
+    RETCK(ensure(ctx, WB_A1, b));
+    RETCK(ensure(ctx, WB_A2, b));
+    {
+        Prof pr(ctx, BCG_K_CONVERT);
+        HIPCK(launch_canon_to_int((const double2*)in, Prec::FP64, W(ctx, WB_A0), nrhs, (int)ctx->Vh, ctx->stream));
+    }
+    RETCK(apply64(ctx, W(ctx, WB_A0), W(ctx, WB_A1), W(ctx, WB_A2), nrhs, nullptr));
+    Prof pr(ctx, BCG_K_CONVERT);
+    HIPCK(launch_int_to_canon(Prec::FP64, W(ctx, WB_A1), (double2*)out, nrhs, (int)ctx->Vh, ctx->stream));
+    return BCG_OK;
+}
+
+int bcg_hop(bcg_ctx* ctx, int out_parity, const void* in, void* out, int nrhs) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (!in || !out) return fail(ctx, BCG_ERR_ARG, "null vector pointer");
+    if (out_parity != 0 && out_parity != 1) return fail(ctx, BCG_ERR_ARG, "out_parity must be 0 or 1");
+    RETCK(check_nrhs(ctx, nrhs));
+    RETCK(check_ready(ctx));
+    const size_t b = (size_t)nvec(ctx, nrhs) * 16;
+    RETCK(ensure(ctx, WB_A0, b));
+    RETCK(ensure(ctx, WB_A1, b));
+    {
+        Prof pr(ctx, BCG_K_CONVERT);
+        HIPCK(launch_canon_to_int((const double2*)in, Prec::FP64, W(ctx, WB_A0), nrhs, (int)ctx->Vh, ctx->stream));
+    }
+    RETCK(hop(ctx, Prec::FP64, out_parity, W(ctx, WB_A0), W(ctx, WB_A1), nullptr, nrhs, EPI_PLAIN_, nullptr));
+    Prof pr(ctx, BCG_K_CONVERT);
+    HIPCK(launch_int_to_canon(Prec::FP64, W(ctx, WB_A1), (double2*)out, nrhs, (int)ctx->Vh, ctx->stream));
+    return BCG_OK;
+}
+
+int bcg_link_force(bcg_ctx* ctx, const void* X, const void* Lam, int nrhs, void* grad_fat,
+                   void* grad_long) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (!X || !Lam || !grad_fat || (ctx->improved && !grad_long))
+        return fail(ctx, BCG_ERR_ARG, "null pointer");
+    RETCK(check_nrhs(ctx, nrhs));
+    RETCK(check_ready(ctx));
+    const size_t b = (size_t)nvec(ctx, nrhs) * 16;
+    for (int s : {WB_A0, WB_A1, WB_A2, WB_A3}) RETCK(ensure(ctx, s, b));
+    {
+        Prof pr(ctx, BCG_K_CONVERT);
+        HIPCK(launch_canon_to_int((const double2*)X, Prec::FP64, W(ctx, WB_A0), nrhs, (int)ctx->Vh, ctx->stream));
+        HIPCK(launch_canon_to_int((const double2*)Lam, Prec::FP64, W(ctx, WB_A1), nrhs, (int)ctx->Vh, ctx->stream));
+    }
+    RETCK(hop(ctx, Prec::FP64, 1, W(ctx, WB_A0), W(ctx, WB_A2), nullptr, nrhs, EPI_PLAIN_, nullptr));
+    RETCK(hop(ctx, Prec::FP64, 1, W(ctx, WB_A1), W(ctx, WB_A3), nullptr, nrhs, EPI_PLAIN_, nullptr));
+    Prof pr(ctx, BCG_K_OTHER);
+    HIPCK(launch_link_force(Wd(ctx, WB_A0), Wd(ctx, WB_A1), Wd(ctx, WB_A2), Wd(ctx, WB_A3), nrhs,
+                            ctx->g, ctx->improved, (double2*)grad_fat, (double2*)grad_long,
+                            ctx->stream));
+    return BCG_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// blockCGrQ
+// ---------------------------------------------------------------------------------------------
+int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, bcg_stats* stats) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (!B || !Xout) return fail(ctx, BCG_ERR_ARG, "null vector pointer");
+    RETCK(check_nrhs(ctx, nrhs));
+    RETCK(check_ready(ctx));
+    const auto t0 = std::chrono::steady_clock::now();
+    const int N = nrhs;
+    const Prec ps = ctx->sloppy;
+    RETCK(alloc_solve(ctx, N, ps));
+    RETCK(ensure_sloppy_links(ctx, ps));
+    const int Vh = (int)ctx->Vh;
+    const long n = nvec(ctx, N);
+    hipStream_t s = ctx->stream;
+    SolveState* st = ctx->d_state;
+    const int* halt = &st->halt;
+    double* d_bnorm = ctx->d_vec;
+    double* d_true = ctx->d_vec + MAXN;
+    int* ru_skip = ctx->d_flags;
+    double2 *B64 = Wd(ctx, WB_B64), *Y = Wd(ctx, WB_Y), *X = Wd(ctx, WB_X), *R64 = Wd(ctx, WB_R64),
+            *T64 = Wd(ctx, WB_T64);
+    void* Pb[2] = {W(ctx, WB_P0), W(ctx, WB_P1)};
+    void* Qb[2] = {W(ctx, WB_Q0), W(ctx, WB_Q1)};
+    void *AP = W(ctx, WB_AP), *T = W(ctx, WB_T);
+
+    {
+        Prof pr(ctx, BCG_K_CONVERT);
+        HIPCK(launch_canon_to_int((const double2*)B, Prec::FP64, B64, N, Vh, s));
+    }
+    RETCK(colnorms(ctx, B64, N, d_bnorm));
+    HIPCK(hipMemcpyAsync(ctx->h_vec, d_bnorm, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    RETCK(sync(ctx));
+    for (int i = 0; i < N; ++i)
+        if (!(ctx->h_vec[i] > 0.0) || !std::isfinite(ctx->h_vec[i]))
+            return fail(ctx, BCG_ERR_ARG, "right-hand side column " + std::to_string(i) + " is zero or not finite");
+
+    HIPCK(launch_zero(X, n * 16, s));
+    if (use_guess) {
+        HIPCK(launch_canon_to_int((const double2*)Xout, Prec::FP64, Y, N, Vh, s));
+        RETCK(apply64(ctx, Y, R64, T64, N, nullptr));
+        HIPCK(launch_residual(B64, R64, n, s));
+    } else {
+        HIPCK(launch_zero(Y, n * 16, s));
+        HIPCK(launch_copy(B64, R64, n * 16, s));
+    }
+    HIPCK(launch_state_init(st, ctx->tol, ctx->ru_delta, d_bnorm, N, s));
+    // thin QR of the initial residual (Alg. 2), Q = R C^{-1}, P = Q (S = I, P_0 = 0)
+    RETCK(gram(ctx, Prec::FP64, R64, R64, N, M(ctx, M_H), nullptr));
+    {
+        Prof pr(ctx, BCG_K_SMALL);
+        HIPCK(launch_small_init(M(ctx, M_H), M(ctx, M_C), M(ctx, M_CINV), st, N, s));
+    }
+    int cur = 0;
+    {
+        Prof pr(ctx, BCG_K_OTHER);
+        HIPCK(launch_bmul(Prec::FP64, R64, ps, nullptr, Qb[cur], M(ctx, M_CINV), N, Vh, halt, s));
+        HIPCK(launch_copy(Qb[cur], Pb[cur], n * (long)prec_bytes(ps), s));
+    }
+    RETCK(read_state(ctx));
+    int status = BCG_OK;
+    int n_ru = 0;
+    int iters_done = 0;
+    if (ctx->h_state->halt) {
+        status = BCG_ERR_BREAKDOWN;
+        fail(ctx, status, "initial residual block is rank deficient (dependent right-hand sides)");
+    } else if (ctx->h_state->max_relres <= ctx->tol) {
+        // X0 already solves the system
+        status = BCG_OK;
+    }
+
+    // convergence-rate bookkeeping for the chunk size
+    double last_log = std::log(std::fmax(ctx->h_state->max_relres, 1e-300));
+    int last_it = 0;
+    double rate = -0.02;   // log-residual change per iteration, refined as the solve runs
+    int iters_at_resume = 0;
+    bool finished = (status != BCG_OK) || (ctx->h_state->max_relres <= ctx->tol);
+    bool need_final_check = true;   // cleared when a reliable update has confirmed convergence
+
+    while (!finished) {
+        const SolveState& hs = *ctx->h_state;
+        // chunk size from the estimated iterations to the next event
+        const double cur_log = std::log(std::fmax(hs.max_relres, 1e-300));
+        double target = std::log(ctx->tol);
+        if (ctx->ru_delta > 0.0) target = std::fmax(target, std::log(ctx->ru_delta * hs.rho_ru));
+        int est = (int)std::ceil((target - cur_log) / (rate < -1e-6 ? rate : -1e-6));
+        int chunk = est < 2 ? 2 : (est > 48 ? 48 : est);
+        if (chunk > ctx->max_iter - hs.iters) chunk = ctx->max_iter - hs.iters;
+        if (chunk < 1) chunk = 1;
+        int c = cur;
+        for (int k = 0; k < chunk; ++k) {
+            void *P = Pb[c], *Q = Qb[c], *Pn = Pb[1 - c], *Qn = Qb[1 - c];
+            RETCK(hop(ctx, ps, 1, P, T, nullptr, N, EPI_PLAIN_, halt));
+            RETCK(hop(ctx, ps, 0, T, AP, P, N, EPI_MASS_, halt));
+            RETCK(gram(ctx, ps, P, AP, N, M(ctx, M_G), halt));
+            {
+                Prof pr(ctx, BCG_K_SMALL);
+                HIPCK(launch_small1(M(ctx, M_G), M(ctx, M_C), M(ctx, M_BETA), M(ctx, M_BETAC), st, N, s));
+            }
+            {
+                Prof pr(ctx, BCG_K_PASS_A);
+                HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, s));
+            }
+            RETCK(gram(ctx, ps, Q, Q, N, M(ctx, M_H), halt));
+            {
+                Prof pr(ctx, BCG_K_SMALL);
+                HIPCK(launch_small2(M(ctx, M_H), M(ctx, M_C), M(ctx, M_SINV), M(ctx, M_SH), st, N, s));
+            }
+            {
+                Prof pr(ctx, BCG_K_PASS_B);
+                HIPCK(launch_pass_b(ps, X, Q, P, Qn, Pn, M(ctx, M_BETAC), M(ctx, M_SINV), M(ctx, M_SH),
+                                    N, Vh, st, s));
+            }
+            c = 1 - c;
+        }
+        RETCK(read_state(ctx));
+        const int active = hs.iters - iters_at_resume;
+        const bool halted = hs.halt != 0;
+        const int reason = hs.reason;
+        const int full = (halted && (reason == HALT_CONVERGED || reason == HALT_RU || reason == HALT_BREAKDOWN_H))
+                             ? active - 1 : active;
+        cur = (cur + full) & 1;
+        iters_at_resume = hs.iters;
+        iters_done = hs.iters;
+        {
+            const double lg = std::log(std::fmax(hs.max_relres, 1e-300));
+            if (hs.iters > last_it) {
+                const double r = (lg - last_log) / (hs.iters - last_it);
+                if (r < 0) rate = r;
+                last_log = lg;
+                last_it = hs.iters;
+            }
+        }
+        if (halted && (reason == HALT_BREAKDOWN_G || reason == HALT_BREAKDOWN_H)) {
+            status = BCG_ERR_BREAKDOWN;
+            fail(ctx, status, "Cholesky breakdown before convergence (rank-deficient block)");
+            break;
+        }
+        if (!halted) {
+            if (hs.iters >= ctx->max_iter) {
+                status = BCG_ERR_NOT_CONVERGED;
+                fail(ctx, status, "max_iter reached");
+                break;
+            }
+            continue;
+        }
+        // reliable update (Alg. 3), also the convergence check on the true residual
+        HIPCK(launch_fold_x(Y, X, n, s));
+        RETCK(apply64(ctx, Y, R64, T64, N, nullptr));
+        HIPCK(launch_residual(B64, R64, n, s));
+        RETCK(gram(ctx, Prec::FP64, R64, R64, N, M(ctx, M_HR), nullptr));
+        {
+            Prof pr(ctx, BCG_K_SMALL);
+            HIPCK(launch_small_ru(M(ctx, M_HR), M(ctx, M_C), M(ctx, M_CINV), M(ctx, M_SH), st, d_true,
+                                  ru_skip, reason == HALT_CONVERGED ? 1 : 0, N, s));
+        }
+        {
+            Prof pr(ctx, BCG_K_OTHER);
+            HIPCK(launch_bmul(Prec::FP64, R64, ps, nullptr, Qb[1 - cur], M(ctx, M_CINV), N, Vh, ru_skip, s));
+            HIPCK(launch_bmul(ps, Pb[cur], ps, Qb[1 - cur], Pb[1 - cur], M(ctx, M_SH), N, Vh, ru_skip, s));
+        }
+        RETCK(read_state(ctx));
+        if (hs.reason == HALT_DONE) {
+            finished = true;
+            need_final_check = false;
+            break;
+        }
+        if (hs.halt) {
+            status = BCG_ERR_BREAKDOWN;
+            fail(ctx, status, "Cholesky breakdown in the reliable update (rank-deficient residual)");
+            break;
+        }
+        cur = 1 - cur;
+        n_ru += 1;
+        last_log = std::log(std::fmax(hs.max_relres, 1e-300));
+        last_it = hs.iters;
+        if (hs.iters >= ctx->max_iter) {
+            status = BCG_ERR_NOT_CONVERGED;
+            fail(ctx, status, "max_iter reached");
+            break;
+        }
+    }
+    // the solution: Y (+ X if the loop ended without folding it)
+    if (status != BCG_OK || need_final_check) {
+        HIPCK(launch_fold_x(Y, X, n, s));
+        RETCK(apply64(ctx, Y, R64, T64, N, nullptr));
+        HIPCK(launch_residual(B64, R64, n, s));
+        RETCK(colnorms(ctx, R64, N, d_true));
+        // relative: divide on the host below
+    }
+    {
+        Prof pr(ctx, BCG_K_CONVERT);
+        HIPCK(launch_int_to_canon(Prec::FP64, Y, (double2*)Xout, N, Vh, s));
+    }
+    HIPCK(hipMemcpyAsync(ctx->h_vec, d_true, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(ctx->h_vec + MAXN, d_bnorm, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    RETCK(sync(ctx));
+    double tr[MAXN];
+    for (int i = 0; i < N; ++i) {
+        tr[i] = ctx->h_vec[i];
+        if (status != BCG_OK || need_final_check) tr[i] /= ctx->h_vec[MAXN + i];
+    }
+    if (status == BCG_OK && need_final_check) {
+        // only reached when the loop ended without a true-residual check (X0 already solved it)
+        for (int i = 0; i < N; ++i)
+            if (tr[i] > ctx->tol) status = BCG_ERR_NOT_CONVERGED;
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(stats, iters_done, n_ru, status, 0, secs, tr, N);
+    return status;
+}
+
+// ---------------------------------------------------------------------------------------------
+// N independent CG solves, one after the other (the baseline)
+// ---------------------------------------------------------------------------------------------
+int bcg_solve_cg(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, bcg_stats* stats) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (!B || !Xout) return fail(ctx, BCG_ERR_ARG, "null vector pointer");
+    RETCK(check_nrhs(ctx, nrhs));
+    RETCK(check_ready(ctx));
+    if (ctx->sloppy != Prec::FP64) return fail(ctx, BCG_ERR_ARG, "the CG baseline runs in FP64 storage only");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int N = nrhs;
+    const int Vh = (int)ctx->Vh;
+    const long n1 = 3L * Vh;
+    hipStream_t s = ctx->stream;
+    RETCK(alloc_solve(ctx, N, Prec::FP64));
+    double2 *B64 = Wd(ctx, WB_B64), *Xs = Wd(ctx, WB_Y), *R64 = Wd(ctx, WB_R64), *T64 = Wd(ctx, WB_T64);
+    double2 *r = Wd(ctx, WB_P0), *p = Wd(ctx, WB_Q0), *Ap = Wd(ctx, WB_AP), *t = Wd(ctx, WB_T);
+    CgState* st = ctx->d_cg;
+    const int* halt = &st->halt;
+    double* dot = ctx->nparts + ctx->dot_off;
+    double* d_true = ctx->d_vec + MAXN;
+    {
+        Prof pr(ctx, BCG_K_CONVERT);
+        HIPCK(launch_canon_to_int((const double2*)B, Prec::FP64, B64, N, Vh, s));
+    }
+    RETCK(colnorms(ctx, B64, N, ctx->d_vec));
+    HIPCK(hipMemcpyAsync(ctx->h_vec, ctx->d_vec, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    RETCK(sync(ctx));
+    double bn[MAXN];
+    for (int i = 0; i < N; ++i) {
+        bn[i] = ctx->h_vec[i];
+        if (!(bn[i] > 0.0) || !std::isfinite(bn[i]))
+            return fail(ctx, BCG_ERR_ARG, "right-hand side column " + std::to_string(i) + " is zero or not finite");
+    }
+    int status = BCG_OK;
+    int total_iters = 0, restarts = 0;
+    double tr[MAXN];
+    const int nparts = hop_dot_blocks(ctx->g);
+    for (int i = 0; i < N && status == BCG_OK; ++i) {
+        const double2* b = B64 + (long)i * n1;
+        double2* x = Xs + (long)i * n1;
+        HIPCK(launch_zero(x, n1 * 16, s));
+        HIPCK(launch_copy(b, r, n1 * 16, s));
+        HIPCK(launch_copy(b, p, n1 * 16, s));
+        HIPCK(launch_colnorm2(b, 1, Vh, ctx->nparts, s));
+        HIPCK(launch_cg_init(ctx->nparts, Vh, st, ctx->tol, 0, s));
+        double rate = -0.02, last_log = 0.0;
+        int last_it = 0;
+        for (;;) {
+            HIPCK(hipMemcpyAsync(ctx->h_cg, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+            RETCK(sync(ctx));
+            const CgState hc = *ctx->h_cg;
+            if (hc.halt) {
+                if (hc.reason == HALT_BREAKDOWN_G) {
+                    status = BCG_ERR_BREAKDOWN;
+                    fail(ctx, status, "CG breakdown: p^H A p <= 0");
+                    break;
+                }
+                // converged on the iterated residual: check the true residual
+                RETCK(apply64(ctx, x, R64, T64, 1, nullptr));
+                HIPCK(launch_residual(b, R64, n1, s));
+                HIPCK(launch_colnorm2(R64, 1, Vh, ctx->nparts, s));
+                HIPCK(launch_colnorm_reduce(ctx->nparts, 1, Vh, d_true + i, 1, s));
+                HIPCK(hipMemcpyAsync(ctx->h_vec, d_true + i, sizeof(double), hipMemcpyDeviceToHost, s));
+                RETCK(sync(ctx));
+                tr[i] = ctx->h_vec[0] / bn[i];
+                if (tr[i] <= ctx->tol) break;
+                // restart from the true residual
+                HIPCK(launch_copy(R64, r, n1 * 16, s));
+                HIPCK(launch_copy(R64, p, n1 * 16, s));
+                HIPCK(launch_cg_init(ctx->nparts, Vh, st, ctx->tol, 1, s));
+                restarts += 1;
+                continue;
+            }
+            if (hc.iters >= ctx->max_iter) {
+                status = BCG_ERR_NOT_CONVERGED;
+                fail(ctx, status, "max_iter reached in CG");
+                break;
+            }
+            const double lg = std::log(std::fmax(hc.relres, 1e-300));
+            if (hc.iters > last_it) {
+                const double rr = (lg - last_log) / (hc.iters - last_it);
+                if (rr < 0) rate = rr;
+            }
+            last_log = lg;
+            last_it = hc.iters;
+            int est = (int)std::ceil((std::log(ctx->tol) - lg) / (rate < -1e-6 ? rate : -1e-6));
+            int chunk = est < 2 ? 2 : (est > 64 ? 64 : est);
+            if (chunk > ctx->max_iter - hc.iters) chunk = ctx->max_iter - hc.iters;
+            for (int k = 0; k < chunk; ++k) {
+                RETCK(hop(ctx, Prec::FP64, 1, p, t, nullptr, 1, EPI_PLAIN_, halt));
+                RETCK(hop(ctx, Prec::FP64, 0, t, Ap, p, 1, EPI_MASS_DOT_, halt, dot));
+                Prof pr(ctx, BCG_K_CG_VEC);
+                HIPCK(launch_cg_alpha(dot, nparts, st, s));
+                HIPCK(launch_cg_update1(x, r, p, Ap, n1, ctx->nparts, st, s));
+                HIPCK(launch_cg_beta(ctx->nparts, n1, st, s));
+                HIPCK(launch_cg_update2(p, r, n1, st, s));
+            }
+        }
+        total_iters += ctx->h_cg->iters;
+        if (status != BCG_OK) {
+            for (int j = i; j < N; ++j) tr[j] = 1.0;
+        }
+    }
+    {
+        Prof pr(ctx, BCG_K_CONVERT);
+        HIPCK(launch_int_to_canon(Prec::FP64, Xs, (double2*)Xout, N, Vh, s));
+    }
+    RETCK(sync(ctx));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(stats, total_iters, 0, status, restarts, secs, tr, N);
+    return status;
+}
+
+int bcg_set_profiling(bcg_ctx* ctx, unsigned mask) {
+    if (!ctx) return BCG_ERR_ARG;
+    ctx->prof_mask = mask;
+    return BCG_OK;
+}
+
+int bcg_profile_reset(bcg_ctx* ctx) {
+    if (!ctx) return BCG_ERR_ARG;
+    RETCK(sync(ctx));
+    for (int k = 0; k < BCG_K_COUNT; ++k) {
+        ctx->prof_n[k] = 0;
+        ctx->prof_ms[k] = 0.0;
+    }
+    return BCG_OK;
+}
+
+int bcg_kernel_time(bcg_ctx* ctx, int kernel, long* launches, double* total_ms) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (kernel < 0 || kernel >= BCG_K_COUNT || !launches || !total_ms)
+        return fail(ctx, BCG_ERR_ARG, "bad kernel id or null output");
+    RETCK(sync(ctx));
+    *launches = ctx->prof_n[kernel];
+    *total_ms = ctx->prof_ms[kernel];
+    return BCG_OK;
+}
+
+const char* bcg_last_error(const bcg_ctx* ctx) {
+    if (!ctx) return g_create_err.c_str();
+    return ctx->err.c_str();
+}
+
+}  // extern "C"

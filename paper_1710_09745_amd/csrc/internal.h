@@ -1,0 +1,118 @@
+// Host-side declarations shared by the library's translation units: the
+// launchers of every gfx950 kernel and the constants of the solver's layouts.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace bcg {
+
+enum class Prec { FP64 = 0, FP32 = 1, FP16 = 2, BF16 = 3 };
+
+constexpr int MAXN = 64;          // largest block size; N x N matrices use leading dimension 64
+constexpr int GRAM_BLOCKS = 512;  // workgroups of a Gram reduction (= rows of its partials)
+constexpr int NORM_BLOCKS = 512;  // workgroups of a column-norm reduction
+
+struct HopShape {
+    int tr;   // right-hand sides per lane (register tile)
+    int tpb;  // right-hand-side tiles per workgroup (cache tile)
+};
+
+// padded block size used to instantiate the N-dependent kernels: 1, 2, 4, ..., 64
+inline int pad_n(int n) {
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// hop.hip ---------------------------------------------------------------------------------------
+hipError_t pack_links(Prec prec, const void* fat, const void* lng, void* W, const Geom& g,
+                      int parity, int nl, hipStream_t s);
+HopShape hop_shape(int N);
+int hop_dot_blocks(const Geom& g);
+hipError_t launch_hop(Prec prec, int nl, const void* W, const void* in, void* out, const void* ctr,
+                      double m2, int N, const Geom& g, int out_parity, int epi, const HopShape& h,
+                      const int* halt, double* dot, hipStream_t s);
+enum { EPI_PLAIN_ = 0, EPI_MASS_ = 1, EPI_MASS_DOT_ = 2 };
+
+// blas.hip --------------------------------------------------------------------------------------
+// partials[b][i*NB + j] = sum over the rows of workgroup b of conj(A[row,i]) B[row,j]
+hipError_t launch_gram(Prec prec, const void* A, const void* B, int N, int Vh, double2* partials,
+                       const int* halt, hipStream_t s);
+// out[i*64 + j] = sum_b partials[b][i*NB + j]  (fixed order)
+hipError_t launch_gram_reduce(const double2* partials, int N, int Vh, double2* out,
+                              const int* halt, hipStream_t s);
+// Q <- Q - AP beta    (beta: [64][64] FP64)
+hipError_t launch_pass_a(Prec prec, void* Q, const void* AP, const double2* beta, int N, int Vh,
+                         const int* halt, hipStream_t s);
+// X += P betaC; Qn <- Qt Sinv; Pn <- Qn + P S^H, as selected by state->pb_mode
+hipError_t launch_pass_b(Prec prec, double2* X, const void* Qt, const void* P, void* Qn, void* Pn,
+                         const double2* betaC, const double2* Sinv, const double2* SH, int N,
+                         int Vh, const SolveState* state, hipStream_t s);
+// Y <- Z + X M  (Z may be NULL = 0; X, Z may alias Y); X in precision px, Y/Z in py
+hipError_t launch_bmul(Prec px, const void* X, Prec py, const void* Z, void* Y, const double2* M,
+                       int N, int Vh, const int* skip, hipStream_t s);
+// canonical [N][Vh][3] complex128 <-> internal [N][3][Vh] pairs
+hipError_t launch_canon_to_int(const double2* src, Prec pd, void* dst, int N, int Vh, hipStream_t s);
+hipError_t launch_int_to_canon(Prec ps, const void* src, double2* dst, int N, int Vh, hipStream_t s);
+// internal FP64 <-> sloppy copy (same layout)
+hipError_t launch_convert(Prec ps, const void* src, Prec pd, void* dst, long n, hipStream_t s);
+// Y += X; X = 0 (FP64)
+hipError_t launch_fold_x(double2* Y, double2* X, long n, hipStream_t s);
+// R <- B - R (FP64)
+hipError_t launch_residual(const double2* B, double2* R, long n, hipStream_t s);
+// per-column ||V_i||^2 partials [NORM_BLOCKS][N]; then reduce into out[N] (sqrt if take_sqrt)
+hipError_t launch_colnorm2(const double2* V, int N, int Vh, double* partials, hipStream_t s);
+hipError_t launch_colnorm_reduce(const double* partials, int N, int Vh, double* out,
+                                 int take_sqrt, hipStream_t s);
+hipError_t launch_zero(void* p, long bytes, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, long bytes, hipStream_t s);
+
+// CG baseline (one right-hand side, FP64)
+struct CgState {
+    int halt;
+    int reason;
+    int iters;
+    int pad;
+    double rr;      // ||r||^2
+    double alpha;
+    double beta;
+    double bnorm;
+    double tol;
+    double relres;
+};
+hipError_t launch_cg_alpha(const double* dot_partials, int nparts, CgState* st, hipStream_t s);
+hipError_t launch_cg_update1(double2* x, double2* r, const double2* p, const double2* Ap, long n,
+                             double* partials, CgState* st, hipStream_t s);
+hipError_t launch_cg_beta(const double* partials, long n, CgState* st, hipStream_t s);
+hipError_t launch_cg_update2(double2* p, const double2* r, long n, CgState* st, hipStream_t s);
+// rr = ||r||^2 from colnorm partials of a Vh-site field (restart keeps ||b|| and iters)
+hipError_t launch_cg_init(const double* partials, int Vh, CgState* st, double tol, int restart,
+                          hipStream_t s);
+
+// small.hip -------------------------------------------------------------------------------------
+hipError_t small_setup();
+// initial thin QR of R from H = R^H R:  C (upper) and Cinv; relres, rho_ru; halts on breakdown
+hipError_t launch_small_init(const double2* H, double2* C, double2* Cinv, SolveState* st, int N,
+                             hipStream_t s);
+// beta = G^{-1}, betaC = beta C
+hipError_t launch_small1(const double2* G, const double2* C, double2* beta, double2* betaC,
+                         SolveState* st, int N, hipStream_t s);
+// residual test, S from H = S^H S, Sinv, S^H, C <- S C; sets pb_mode / halt
+hipError_t launch_small2(const double2* H, double2* C, double2* Sinv, double2* SH, SolveState* st,
+                         int N, hipStream_t s);
+// reliable update from H = R^H R of the true residual: true residuals; if conv_check and
+// all <= tol: done; else C^ , C^-1, S^H = (C^ C^-1)^H, C <- C^, resume
+hipError_t launch_small_ru(const double2* H, double2* C, double2* Chinv, double2* SH,
+                           SolveState* st, double* true_relres, int* ru_skip, int conv_check,
+                           int N, hipStream_t s);
+hipError_t launch_state_init(SolveState* st, double tol, double ru_delta, const double* bnorm,
+                             int N, hipStream_t s);
+hipError_t launch_identity(double2* M, int N, hipStream_t s);
+
+// force.hip -------------------------------------------------------------------------------------
+hipError_t launch_link_force(const double2* X, const double2* Lam, const double2* YX,
+                             const double2* YL, int N, const Geom& g, int improved,
+                             double2* gfat, double2* glong, hipStream_t s);
+
+}  // namespace bcg

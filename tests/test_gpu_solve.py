@@ -1,0 +1,186 @@
+"""GPU parity of blockCGrQ and the CG baseline against the CPU oracle.
+
+The solution of A X = B is unique, so the bar is the true relative residual of
+every column computed with the oracle's FP64 operator (<= 1e-10 in FP64 mode,
+<= 1e-8 in mixed precision) plus the distance to the oracle's own solution
+(solved to 1e-12), bounded by the condition number.  The first iterates are
+unique too (the CholQR factors have positive real diagonals), so X after k
+iterations is compared with the oracle's X after k iterations."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1710_09745_amd import bcg, synth
+
+from gpu_util import DEV, col_rel_err, context, inputs, kappa_bound, to_dev, true_rel_res
+
+pytestmark = pytest.mark.gpu
+
+
+def test_config1_solve_matches_oracle_and_dense_solve():
+    c = synth.CONFIGS[1]
+    fat, lng, B = synth.config_inputs(1)
+    ctx = context(c["dims"], False, fat, lng, c["mass"], tol=c["tol"])
+    X, info = ctx.solve(to_dev(B))
+    X = X.cpu().numpy()
+    op = oracle.Operator(c["dims"], fat, lng, c["mass"])
+    assert true_rel_res(op, B, X).max() <= c["tol"]
+    assert max(info["true_rel_res"]) <= c["tol"]
+    Xo, _ = oracle.block_cg_rq(op.apply, B, 1e-12)
+    from test_oracle_operator import dense_A
+    A = dense_A(op)
+    kappa = np.linalg.cond(A)
+    Xd = oracle.from_mat(np.linalg.solve(A, oracle.to_mat(B)), op.Vh)
+    err = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
+    print(f"config 1: iters={info['iters']} rus={info['reliable_updates']} "
+          f"||X-X_oracle||/||X_oracle||={err:.2e} kappa={kappa:.1f}")
+    assert err <= kappa * c["tol"]
+    assert np.linalg.norm(X - Xd) / np.linalg.norm(Xd) <= kappa * c["tol"]
+
+
+@pytest.mark.parametrize("dims,improved,m,n", [((6, 6, 6, 6), True, 0.1, 5),
+                                               ((8, 8, 8, 8), True, 0.1, 16),
+                                               ((4, 6, 4, 8), False, 0.2, 1),
+                                               ((8, 8, 8, 8), True, 0.2, 64)])
+def test_solve_matches_oracle(dims, improved, m, n):
+    fat, lng, B = inputs(dims, improved, n, 4000 + n)
+    ctx = context(dims, improved, fat, lng, m, tol=1e-10)
+    X, info = ctx.solve(to_dev(B))
+    X = X.cpu().numpy()
+    op = oracle.Operator(dims, fat, lng, m)
+    res = true_rel_res(op, B, X)
+    assert res.max() <= 1e-10
+    assert np.allclose(res, info["true_rel_res"], rtol=1e-3, atol=1e-14)
+    Xo, io = oracle.block_cg_rq(op.apply, B, 1e-12)
+    err = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
+    kappa = kappa_bound(op)
+    print(f"iters gpu={info['iters']} oracle={io.iters} err={err:.2e} kappa<={kappa:.0f}")
+    assert err <= kappa * 1e-10
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8])
+def test_iterates_match_oracle(k):
+    dims = (6, 4, 6, 6)
+    fat, lng, B = inputs(dims, True, 6, 5000)
+    m = 0.1
+    ctx = context(dims, True, fat, lng, m, tol=1e-14, ru_delta=0.0, max_iter=k)
+    X, info = ctx.solve(to_dev(B), raise_on_error=False)
+    assert info["rc"] == bcg.ERR_NOT_CONVERGED and info["iters"] == k
+    op = oracle.Operator(dims, fat, lng, m)
+    Xo, io = oracle.block_cg_rq(op.apply, B, 1e-14, max_iter=k)
+    assert col_rel_err(X.cpu().numpy(), Xo).max() <= 1e-10
+
+
+def test_cg_baseline_matches_oracle():
+    dims = (6, 6, 6, 6)
+    fat, lng, B = inputs(dims, True, 3, 6000)
+    m = 0.1
+    ctx = context(dims, True, fat, lng, m, tol=1e-10)
+    X, info = ctx.solve_cg(to_dev(B))
+    X = X.cpu().numpy()
+    op = oracle.Operator(dims, fat, lng, m)
+    assert true_rel_res(op, B, X).max() <= 1e-10
+    its = 0
+    kappa = kappa_bound(op)
+    for i in range(3):
+        xo, io = oracle.cg(op.apply, B[i], 1e-10)
+        its += io.iters
+        assert np.linalg.norm(X[i] - xo) / np.linalg.norm(xo) <= kappa * 2e-10
+    print(f"cg iters gpu={info['iters']} oracle={its}")
+    assert abs(info["iters"] - its) <= 3 * 3
+
+
+def test_n1_block_equals_cg():
+    dims = (6, 6, 4, 4)
+    fat, lng, B = inputs(dims, True, 1, 6100)
+    ctx = context(dims, True, fat, lng, 0.15, tol=1e-11, ru_delta=0.0)
+    Xb, ib = ctx.solve(to_dev(B))
+    Xc, ic = ctx.solve_cg(to_dev(B))
+    assert abs(ib["iters"] - ic["iters"]) <= 2
+    assert col_rel_err(Xb.cpu().numpy(), Xc.cpu().numpy()).max() <= 1e-9
+
+
+def test_solve_is_deterministic():
+    dims = (8, 8, 8, 8)
+    fat, lng, B = inputs(dims, True, 8, 6200)
+    ctx = context(dims, True, fat, lng, 0.1, tol=1e-10)
+    X1, i1 = ctx.solve(to_dev(B))
+    X2, i2 = ctx.solve(to_dev(B))
+    assert i1["iters"] == i2["iters"]
+    assert torch.equal(X1, X2)
+
+
+def test_initial_guess():
+    dims = (6, 6, 6, 6)
+    fat, lng, B = inputs(dims, True, 4, 6300)
+    ctx = context(dims, True, fat, lng, 0.1, tol=1e-10)
+    X, info = ctx.solve(to_dev(B))
+    X2, info2 = ctx.solve(to_dev(B), X0=X)
+    assert info2["iters"] <= 1
+    op = oracle.Operator(dims, fat, lng, 0.1)
+    assert true_rel_res(op, B, X2.cpu().numpy()).max() <= 1e-10
+
+
+def test_error_paths():
+    dims = (4, 4, 4, 4)
+    fat, lng, B = inputs(dims, True, 4, 6400)
+    ctx = bcg.Context(dims, improved=True, device=DEV)
+    with pytest.raises(bcg.BcgError) as e:
+        ctx.solve(to_dev(B))
+    assert e.value.code == bcg.ERR_STATE
+    ctx.load_links(fat, lng)
+    ctx.set_mass(0.1)
+    ctx.set_solver(tol=1e-10, max_iter=1000)
+    Bz = B.copy()
+    Bz[2] = 0
+    with pytest.raises(bcg.BcgError) as e:
+        ctx.solve(to_dev(Bz))
+    assert e.value.code == bcg.ERR_ARG
+    Bd = B.copy()
+    Bd[3] = Bd[1]
+    with pytest.raises(bcg.Breakdown):
+        ctx.solve(to_dev(Bd))
+    ctx.set_solver(tol=1e-10, max_iter=2)
+    with pytest.raises(bcg.NotConverged):
+        ctx.solve(to_dev(B))
+    big = torch.zeros((65, ctx.Vh, 3), dtype=torch.complex128, device=DEV)
+    with pytest.raises(bcg.BcgError) as e:
+        ctx.apply(big)
+    assert e.value.code == bcg.ERR_ARG
+    with pytest.raises(bcg.BcgError) as e:
+        ctx.set_solver(tol=0.0)
+    assert e.value.code == bcg.ERR_ARG
+
+
+def test_mixed_fp32_reaches_tolerance():
+    dims = (8, 8, 8, 8)
+    fat, lng, B = inputs(dims, True, 8, 6500)
+    m = 0.05
+    c64 = context(dims, True, fat, lng, m, tol=1e-8, prec="fp64")
+    X64, i64 = c64.solve(to_dev(B))
+    c32 = context(dims, True, fat, lng, m, tol=1e-8, prec="fp32")
+    X32, i32 = c32.solve(to_dev(B))
+    op = oracle.Operator(dims, fat, lng, m)
+    r32 = true_rel_res(op, B, X32.cpu().numpy())
+    d = np.linalg.norm((X32 - X64).cpu().numpy()) / np.linalg.norm(X64.cpu().numpy())
+    print(f"fp64 iters={i64['iters']} fp32 iters={i32['iters']} rus={i32['reliable_updates']} "
+          f"max res={r32.max():.2e} ||X32-X64||/||X64||={d:.2e}")
+    assert r32.max() <= 1e-8
+    assert i32["reliable_updates"] >= 1
+
+
+def test_config2_full_size_solve_and_cg():
+    c = synth.CONFIGS[2]
+    fat, lng, B = synth.config_inputs(2)
+    ctx = context(c["dims"], True, fat, lng, c["mass"], tol=c["tol"])
+    X, info = ctx.solve(to_dev(B))
+    op = oracle.Operator(c["dims"], fat, lng, c["mass"])
+    res = true_rel_res(op, B, X.cpu().numpy())
+    print(f"config 2 block: iters={info['iters']} rus={info['reliable_updates']} "
+          f"t={info['seconds']:.3f}s max res={res.max():.2e}")
+    assert res.max() <= c["tol"]
+    Xc, ic = ctx.solve_cg(to_dev(B[:2].copy()))
+    resc = true_rel_res(op, B[:2], Xc.cpu().numpy())
+    print(f"config 2 cg (2 columns): iters={ic['iters']} t={ic['seconds']:.3f}s max res={resc.max():.2e}")
+    assert resc.max() <= c["tol"]
