@@ -31,25 +31,31 @@ HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_1710_09745_amd", "csrc")
 
-# Algorithmic bytes per even (or odd) site of one launch, FP64 storage (s = 8 bytes
-# per real), N right-hand sides: each link and each vector moved once.
-#   hop_oe : 16 folded links (288 reals) + read P, write T (12 N reals)
-#   hop_eo : 16 folded links + read T, read P (mass term), write AP (18 N reals)
-#   gram   : read both block vectors (12 N reals), or one when they alias
-#   pass_a : read Q, AP, write Q (18 N reals)
-#   pass_b : read Qt, P, X, write Q, P, X (36 N reals)
-def model_bytes_per_site(kernel, N, s=8, s_link=8, nl=16, aliased_gram=None):
-    link = nl * 18 * s_link
+# Algorithmic bytes per even (or odd) site of one launch with N right-hand sides:
+# every link and every vector element moved once.  vc = bytes per stored complex
+# vector component (16-bit formats include their FP32 scale per 3 components),
+# lm = bytes per stored folded link matrix (16 per site).
+#   hop_oe : 16 link matrices + read P, write T              (6 N components)
+#   hop_eo : 16 link matrices + read T, read P, write AP     (9 N components)
+#   gram   : read both block vectors (6 N), or one when they alias (3 N)
+#   pass_a : read Q, AP, write Q                             (9 N components)
+#   pass_b : read Qt, P, write Q, P (12 N) + read and write the FP64 X (6 N x 16 B)
+VC = {"fp64": 16.0, "fp32": 8.0, "fp16": 4.0 + 4.0 / 3.0, "bf16": 4.0 + 4.0 / 3.0}
+LM = {"fp64": 144.0, "fp32": 72.0, "fp16": 40.0, "bf16": 40.0}
+
+
+def model_bytes_per_site(kernel, N, prec="fp64", nl=16, aliased_gram=None):
+    vc, link = VC[prec], nl * LM[prec]
     if kernel == "hop_oe":
-        return link + 12 * N * s
+        return link + 6 * N * vc
     if kernel == "hop_eo":
-        return link + 18 * N * s
+        return link + 9 * N * vc
     if kernel == "gram":
-        return 6 * N * s if aliased_gram else 12 * N * s
+        return 3 * N * vc if aliased_gram else 6 * N * vc
     if kernel == "pass_a":
-        return 18 * N * s
+        return 9 * N * vc
     if kernel == "pass_b":
-        return 24 * N * s + 12 * N * 8
+        return 12 * N * vc + 6 * N * 16
     return None
 
 
@@ -84,6 +90,12 @@ def main():
     ap.add_argument("--cg-steps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", choices=["config2", "config3"], default="config2",
+                    help="config2: 16^4, N=16, FP64 (default); config3: 32^3x64, FP32 + FP64 "
+                         "reliable updates, tol 1e-8, N from --nrhs")
+    ap.add_argument("--nrhs", type=int, default=16)
+    ap.add_argument("--prec", default=None, help="storage precision override (fp64/fp32/fp16/bf16)")
+    ap.add_argument("--no-cg", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -97,17 +109,26 @@ def main():
 
     from paper_1710_09745_amd import bcg, synth
 
-    c = synth.CONFIGS[2]
-    dims, m, N, tol = c["dims"], c["mass"], c["nrhs"], c["tol"]
-    workload = "16^4 improved staggered (fat N(0,1)/3 + Haar long), m=0.05, N=16, FP64, tol 1e-10"
-    wkey = "config2"
-    fat, lng, B = synth.config_inputs(2)
+    if args.workload == "config2":
+        c = synth.CONFIGS[2]
+        dims, m, N, tol, prec = c["dims"], c["mass"], c["nrhs"], c["tol"], "fp64"
+        fat, lng, B = synth.config_inputs(2)
+    else:
+        c = synth.CONFIGS[3]
+        dims, m, N, tol, prec = c["dims"], c["mass"], args.nrhs, c["tol"], "fp32"
+        fat, lng, B = synth.config_inputs(3, nrhs=N)
+    if args.prec:
+        prec = args.prec
+    wkey = args.workload if args.workload == "config3" or prec != "fp64" else "config2"
+    workload = (f"{'x'.join(str(d) for d in dims)} improved staggered (fat N(0,1)/3 + Haar long), "
+                f"m={m}, N={N}, {prec} storage{' + FP64 reliable updates' if prec != 'fp64' else ''}, "
+                f"tol {tol:g}")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ctx = bcg.Context(dims, improved=True, device=dev)
     ctx.load_links(fat, lng)
     ctx.set_mass(m)
-    ctx.set_solver(tol=tol, max_iter=100000, prec="fp64", ru_delta=0.1)
+    ctx.set_solver(tol=tol, max_iter=100000, prec=prec, ru_delta=0.1)
     Bt = torch.from_numpy(B).to(dev)
     torch.cuda.synchronize()
     print(f"[bench] workload: {workload}", file=sys.stderr, flush=True)
@@ -146,21 +167,24 @@ def main():
     ctx.set_profiling([])
     max_res = info["max_true_rel_res"]
 
-    # CG baseline: N independent solves, same operator and tolerance
-    Xc, ic = ctx.solve_cg(Bt)      # warm
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(args.cg_steps):
-        Xc, ic = ctx.solve_cg(Bt)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    cg_ms = (t3 - t2) * 1e3 / args.cg_steps
-    print(f"[bench] block {ms_per_step:.2f} ms/solve ({iters[-1]} iters), CG {cg_ms:.2f} ms "
-          f"for {N} columns ({ic['iters']} iters)", file=sys.stderr, flush=True)
+    # CG baseline: N independent FP64 solves, same operator and tolerance
+    cg_ms, ic = None, None
+    if not args.no_cg:
+        ctx.set_solver(tol=tol, max_iter=100000, prec="fp64", ru_delta=0.1)
+        Xc, ic = ctx.solve_cg(Bt)      # warm
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.cg_steps):
+            Xc, ic = ctx.solve_cg(Bt)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        cg_ms = (t3 - t2) * 1e3 / args.cg_steps
+        print(f"[bench] block {ms_per_step:.2f} ms/solve ({iters[-1]} iters), CG {cg_ms:.2f} ms "
+              f"for {N} columns ({ic['iters']} iters)", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel
     Vh = synth.volume(dims) // 2
-    per_site = model_bytes_per_site(dominant, N, aliased_gram=None)
+    per_site = model_bytes_per_site(dominant, N, prec)
     launch_bytes = per_site * Vh
     avg_ms = kms / max(launches, 1)
     achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
@@ -172,7 +196,7 @@ def main():
     dslash = {}
     for k in ("hop_oe", "hop_eo"):
         if k in breakdown:
-            b = model_bytes_per_site(k, N) * Vh
+            b = model_bytes_per_site(k, N, prec) * Vh
             t = breakdown[k]["total_ms"] / breakdown[k]["launches"]
             dslash[k] = {"GB/s": round(b / (t * 1e-3) / 1e9, 1),
                          "frac_hbm": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -192,16 +216,16 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "fp16": "f16+f64", "bf16": "bf16+f64"}[prec],
         "data": "synthetic",
         "config": {"workload": workload, "lattice": list(dims), "nrhs": N, "mass": m,
-                   "tol": tol, "storage": "fp64", "parallelism": "single GPU"},
+                   "tol": tol, "storage": prec, "parallelism": "single GPU"},
         "block_iters": iters[-1],
         "block_reliable_updates": info["reliable_updates"],
         "block_max_true_rel_res": max_res,
-        "cg_ms_per_rhs": round(cg_ms / N, 4),
-        "cg_iters_per_rhs": round(ic["iters"] / N, 1),
-        "speedup_vs_cg": round(cg_ms / ms_per_step, 3),
+        "cg_ms_per_rhs": round(cg_ms / N, 4) if cg_ms else None,
+        "cg_iters_per_rhs": round(ic["iters"] / N, 1) if ic else None,
+        "speedup_vs_cg": round(cg_ms / ms_per_step, 3) if cg_ms else None,
         "roofline": roofline,
         "dslash": dslash,
         "kernel_breakdown_warmup_ms": {k: round(v["total_ms"], 3) for k, v in breakdown.items()},
@@ -218,9 +242,9 @@ def cpu_baseline(dims, fat, lng, m, B, tol, gpu_iters, budget_s):
 
     op = oracle.Operator(dims, fat, lng, m)
     t0 = time.perf_counter()
-    op.apply(B)
-    t_apply = time.perf_counter() - t0
-    k = max(2, min(gpu_iters, int(budget_s / max(t_apply * 1.3, 1e-6))))
+    oracle.block_cg_rq(op.apply, B, 1e-30, max_iter=2)
+    t_probe = (time.perf_counter() - t0) / 2
+    k = max(2, min(gpu_iters, int(budget_s / max(t_probe, 1e-6))))
     t0 = time.perf_counter()
     oracle.block_cg_rq(op.apply, B, 1e-30, max_iter=k)
     t = time.perf_counter() - t0

@@ -151,6 +151,19 @@ int bcg_solve_cg(bcg_ctx *ctx, const void *B, void *X, int nrhs, bcg_stats *stat
 int bcg_link_force(bcg_ctx *ctx, const void *X, const void *Lam, int nrhs, void *grad_fat,
                    void *grad_long);
 
+/* Tuning options (launch shapes and kernel variants; results do not depend on
+ * them beyond floating-point rounding order).  value 0 restores the default.
+ *   BCG_OPT_HOP_TR        right-hand sides per lane in the hop (1, 2, 4, 8)
+ *   BCG_OPT_HOP_TPB       lane groups per workgroup sharing sites (1, 2, 4)
+ *   BCG_OPT_HOP_PIPELINE  1: software-pipelined link loop in the hop
+ *   BCG_OPT_PASS_CPT      columns per lane in the streaming passes (1, 2, 4)
+ *   BCG_OPT_FUSE_GRAM     1: Gram products fused into the epilogues of the hop
+ *                         and the streaming passes (G = 4 m^2 P^H P + T^H T)
+ * Returns BCG_ERR_ARG for an unknown option. */
+enum { BCG_OPT_HOP_TR = 0, BCG_OPT_HOP_TPB = 1, BCG_OPT_HOP_PIPELINE = 2, BCG_OPT_PASS_CPT = 3,
+       BCG_OPT_FUSE_GRAM = 4, BCG_OPT_COUNT = 5 };
+int bcg_set_option(bcg_ctx *ctx, int option, int value);
+
 /* Per-kernel timing with HIP events on the context's stream.  mask: bit set of
  * BCG_K_* kernels to time (0 = off).  While on, each launch of a selected
  * kernel is bracketed by two events; bcg_kernel_time returns the number of

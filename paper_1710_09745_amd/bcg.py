@@ -28,6 +28,7 @@ STATUS_NAMES = {OK: "ok", ERR_ARG: "bad argument", ERR_HIP: "HIP error", ERR_NOM
                 ERR_STATE: "bad state"}
 
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
+OPTIONS = {"hop_tr": 0, "hop_tpb": 1, "hop_pipeline": 2, "pass_cpt": 3, "fuse_gram": 4}
 KERNELS = ["hop_oe", "hop_eo", "gram", "reduce", "small", "pass_a", "pass_b", "cg_vec",
            "convert", "other"]
 MAX_RHS = 64
@@ -78,6 +79,7 @@ def load_library():
         "bcg_solve_cg": ([P, P, P, I, ctypes.POINTER(Stats)], I),
         "bcg_link_force": ([P, P, P, I, P, P], I),
         "bcg_set_profiling": ([P, U], I),
+        "bcg_set_option": ([P, I, I], I),
         "bcg_profile_reset": ([P], I),
         "bcg_kernel_time": ([P, I, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D)], I),
         "bcg_last_error": ([P], ctypes.c_char_p),
@@ -244,6 +246,13 @@ class Context:
                                             ctypes.c_void_p(gf.data_ptr()),
                                             ctypes.c_void_p(gl.data_ptr()) if gl is not None else None))
         return gf, gl
+
+    # -- tuning ------------------------------------------------------------------------------
+    def set_option(self, name, value):
+        """Launch-shape / kernel-variant option (see OPTIONS); 0 restores the default."""
+        if name not in OPTIONS:
+            raise ValueError(f"unknown option {name!r}; known: {sorted(OPTIONS)}")
+        self._check(self.lib.bcg_set_option(self.h, OPTIONS[name], int(value)))
 
     # -- profiling ---------------------------------------------------------------------------
     def set_profiling(self, kernels):

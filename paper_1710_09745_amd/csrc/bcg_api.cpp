@@ -59,7 +59,9 @@ struct bcg_ctx {
     CgState* d_cg = nullptr;
     CgState* h_cg = nullptr;        // pinned
     double2* mats = nullptr;        // small matrices, 10 x [64][64]
-    double2* partials = nullptr;    // GRAM_BLOCKS x 64 x 64
+    double2* partials = nullptr;    // 3 x GRAM_BLOCKS x 64 x 64: general / T^H T / P^H P
+    double2* part_tt = nullptr;
+    double2* part_pp = nullptr;
     double* nparts = nullptr;       // NORM_BLOCKS x 64 norm partials, then the CG dot partials
     long dot_off = 0;               // offset of the CG dot partials in nparts
     double* d_vec = nullptr;        // bnorm[64], true_relres[64]
@@ -73,6 +75,8 @@ struct bcg_ctx {
     std::vector<hipEvent_t> pool;
     long prof_n[BCG_K_COUNT]{};
     double prof_ms[BCG_K_COUNT]{};
+    // tuning options (bcg_set_option), 0 = default
+    int opt[BCG_OPT_COUNT]{};
 };
 
 namespace {
@@ -102,14 +106,6 @@ int fail(bcg_ctx* c, int code, const std::string& msg) {
         int r_ = (call);                 \
         if (r_ != BCG_OK) return r_;     \
     } while (0)
-
-size_t prec_bytes(Prec p) {
-    switch (p) {
-        case Prec::FP64: return 16;
-        case Prec::FP32: return 8;
-        default: return 4;
-    }
-}
 
 int ensure(bcg_ctx* ctx, int slot, size_t bytes) {
     Buf& b = ctx->work[slot];
@@ -201,13 +197,33 @@ int check_ready(bcg_ctx* ctx) {
 // ---- building blocks -----------------------------------------------------------------------
 long nvec(bcg_ctx* ctx, int N) { return (long)N * 3 * ctx->Vh; }
 
+HopShape shape(bcg_ctx* ctx, int N) {
+    return hop_shape(N, ctx->opt[BCG_OPT_HOP_TR], ctx->opt[BCG_OPT_HOP_TPB], ctx->opt[BCG_OPT_HOP_PIPELINE]);
+}
+
 int hop(bcg_ctx* ctx, Prec p, int out_parity, const void* in, void* out, const void* ctr, int N,
-        int epi, const int* halt, double* dot = nullptr) {
+        int epi, const int* halt, double* dot = nullptr, double2* partials = nullptr) {
     const void* Wp = (p == Prec::FP64) ? ctx->W64[out_parity] : ctx->Wsl[out_parity];
-    HopShape h = hop_shape(N);
+    HopShape h = shape(ctx, N);
     Prof pr(ctx, out_parity == 1 ? BCG_K_HOP_OE : BCG_K_HOP_EO);
     HIPCK(launch_hop(p, ctx->nl, Wp, in, out, ctr, 4.0 * ctx->mass * ctx->mass, N, ctx->g,
-                     out_parity, epi, h, halt, dot, ctx->stream));
+                     out_parity, epi, h, halt, dot, partials, ctx->stream));
+    return BCG_OK;
+}
+
+// the fused Gram epilogues fit in LDS for this precision and block size
+// The fused epilogues save one read of a block vector per Gram but keep a Gram
+// accumulator live through the streaming loop (lower occupancy); measured slower
+// than the separate Gram kernels on MI355X, so they are opt-in (BCG_OPT_FUSE_GRAM).
+bool fused_ok(bcg_ctx* ctx, Prec p, int N) {
+    if (!ctx->opt[BCG_OPT_FUSE_GRAM]) return false;
+    return hop_tile_bytes(p, N, shape(ctx, N)) > 0 && fused_tile_bytes(p, N) > 0;
+}
+
+int reduce(bcg_ctx* ctx, const double2* pa, int na, const double2* pb, int nb, double alpha, int N,
+           double2* out, const int* halt) {
+    Prof pr(ctx, BCG_K_REDUCE);
+    HIPCK(launch_gram_reduce(pa, na, pb, nb, alpha, N, out, halt, ctx->stream));
     return BCG_OK;
 }
 
@@ -218,14 +234,17 @@ int apply64(bcg_ctx* ctx, const void* in, void* out, void* tmp, int N, const int
     return BCG_OK;
 }
 
-int gram(bcg_ctx* ctx, Prec p, const void* A, const void* B, int N, double2* out, const int* halt) {
-    {
-        Prof pr(ctx, BCG_K_GRAM);
-        HIPCK(launch_gram(p, A, B, N, (int)ctx->Vh, ctx->partials, halt, ctx->stream));
-    }
-    Prof pr(ctx, BCG_K_REDUCE);
-    HIPCK(launch_gram_reduce(ctx->partials, N, (int)ctx->Vh, out, halt, ctx->stream));
+// partials of A^H B into part (count gram_parts(N, Vh))
+int gram_partials(bcg_ctx* ctx, Prec p, const void* A, const void* B, int N, double2* part, const int* halt) {
+    Prof pr(ctx, BCG_K_GRAM);
+    HIPCK(launch_gram(p, A, B, N, (int)ctx->Vh, part, halt, ctx->stream));
     return BCG_OK;
+}
+
+// out = A^H B  (N x N, FP64, leading dimension 64)
+int gram(bcg_ctx* ctx, Prec p, const void* A, const void* B, int N, double2* out, const int* halt) {
+    RETCK(gram_partials(ctx, p, A, B, N, ctx->partials, halt));
+    return reduce(ctx, ctx->partials, gram_parts(N, (int)ctx->Vh), nullptr, 0, 0.0, N, out, halt);
 }
 
 int colnorms(bcg_ctx* ctx, const double2* V, int N, double* out) {
@@ -242,7 +261,7 @@ int read_state(bcg_ctx* ctx) {
 }
 
 int alloc_solve(bcg_ctx* ctx, int N, Prec ps) {
-    const size_t n64 = (size_t)nvec(ctx, N) * 16, nsl = (size_t)nvec(ctx, N) * prec_bytes(ps);
+    const size_t n64 = (size_t)nvec(ctx, N) * 16, nsl = store_bytes(ps, N, 3, ctx->Vh);
     for (int s : {WB_B64, WB_Y, WB_X, WB_R64, WB_T64}) RETCK(ensure(ctx, s, n64));
     for (int s : {WB_P0, WB_P1, WB_Q0, WB_Q1, WB_AP, WB_T}) RETCK(ensure(ctx, s, nsl));
     return BCG_OK;
@@ -250,16 +269,19 @@ int alloc_solve(bcg_ctx* ctx, int N, Prec ps) {
 
 int ensure_sloppy_links(bcg_ctx* ctx, Prec ps) {
     if (ps == Prec::FP64) return BCG_OK;
-    if (ps != Prec::FP32) return fail(ctx, BCG_ERR_ARG, "16-bit storage is not available in this build");
     if (ctx->Wsl[0] && ctx->wsl_prec == ps) return BCG_OK;
-    const long n = (long)ctx->nl * 9 * ctx->Vh;
     for (int p = 0; p < 2; ++p) {
-        if (!ctx->Wsl[p]) {
-            if (hipMalloc(&ctx->Wsl[p], (size_t)n * prec_bytes(ps)) != hipSuccess)
-                return fail(ctx, BCG_ERR_NOMEM, "sloppy link allocation failed");
+        if (ctx->Wsl[p]) {
+            HIPCK(hipStreamSynchronize(ctx->stream));
+            HIPCK(hipFree(ctx->Wsl[p]));
+            ctx->Wsl[p] = nullptr;
+        }
+        if (hipMalloc(&ctx->Wsl[p], store_bytes(ps, ctx->nl, 9, ctx->Vh)) != hipSuccess) {
+            ctx->Wsl[p] = nullptr;
+            return fail(ctx, BCG_ERR_NOMEM, "sloppy link allocation failed");
         }
         Prof pr(ctx, BCG_K_CONVERT);
-        HIPCK(launch_convert(Prec::FP64, ctx->W64[p], ps, ctx->Wsl[p], n, ctx->stream));
+        HIPCK(links_from64(ps, ctx->W64[p], ctx->Wsl[p], ctx->nl, ctx->Vh, ctx->stream));
     }
     ctx->wsl_prec = ps;
     return BCG_OK;
@@ -320,7 +342,7 @@ int bcg_create(bcg_ctx** out, const int dims[4], int improved, void* hip_stream)
               hipMalloc(&ctx->d_cg, sizeof(CgState)) == hipSuccess &&
               hipHostMalloc(&ctx->h_cg, sizeof(CgState)) == hipSuccess &&
               hipMalloc(&ctx->mats, sizeof(double2) * M_COUNT * MAXN * MAXN) == hipSuccess &&
-              hipMalloc(&ctx->partials, sizeof(double2) * GRAM_BLOCKS * MAXN * MAXN) == hipSuccess &&
+              hipMalloc(&ctx->partials, sizeof(double2) * 3 * GRAM_BLOCKS * MAXN * MAXN) == hipSuccess &&
               hipMalloc(&ctx->nparts, sizeof(double) * ((long)NORM_BLOCKS * MAXN + ctx->Vh / 256 + 1)) == hipSuccess &&
               hipMalloc(&ctx->d_vec, sizeof(double) * 4 * MAXN) == hipSuccess &&
               hipMalloc(&ctx->d_flags, sizeof(int) * 16) == hipSuccess &&
@@ -329,6 +351,8 @@ int bcg_create(bcg_ctx** out, const int dims[4], int improved, void* hip_stream)
         bcg_destroy(ctx);
         return fail(nullptr, BCG_ERR_NOMEM, "context allocation failed");
     }
+    ctx->part_tt = ctx->partials + (size_t)GRAM_BLOCKS * MAXN * MAXN;
+    ctx->part_pp = ctx->partials + (size_t)2 * GRAM_BLOCKS * MAXN * MAXN;
     *out = ctx;
     return BCG_OK;
 }
@@ -383,7 +407,7 @@ int bcg_load_links(bcg_ctx* ctx, const void* fat, const void* lng, int on_device
             if (tmp) (void)hipFree(tmp);
             return fail(ctx, BCG_ERR_NOMEM, "link allocation failed");
         }
-        HIPCK(pack_links(Prec::FP64, dfat, dlng, ctx->W64[p], ctx->g, p, ctx->nl, ctx->stream));
+        HIPCK(pack_links(dfat, dlng, ctx->W64[p], ctx->g, p, ctx->nl, ctx->stream));
     }
     ctx->wsl_prec = Prec::FP64;   // sloppy copies are rebuilt from the new links on demand
     if (ctx->Wsl[0]) {
@@ -428,11 +452,11 @@ int bcg_apply(bcg_ctx* ctx, const void* in, void* out, int nrhs) {
     RETCK(ensure(ctx, WB_A2, b));
     {
         Prof pr(ctx, BCG_K_CONVERT);
-        HIPCK(launch_canon_to_int((const double2*)in, Prec::FP64, W(ctx, WB_A0), nrhs, (int)ctx->Vh, ctx->stream));
+        HIPCK(launch_canon_to_int((const double2*)in, Wd(ctx, WB_A0), nrhs, (int)ctx->Vh, ctx->stream));
     }
     RETCK(apply64(ctx, W(ctx, WB_A0), W(ctx, WB_A1), W(ctx, WB_A2), nrhs, nullptr));
     Prof pr(ctx, BCG_K_CONVERT);
-    HIPCK(launch_int_to_canon(Prec::FP64, W(ctx, WB_A1), (double2*)out, nrhs, (int)ctx->Vh, ctx->stream));
+    HIPCK(launch_int_to_canon(Wd(ctx, WB_A1), (double2*)out, nrhs, (int)ctx->Vh, ctx->stream));
     return BCG_OK;
 }
 
@@ -447,11 +471,11 @@ int bcg_hop(bcg_ctx* ctx, int out_parity, const void* in, void* out, int nrhs) {
     RETCK(ensure(ctx, WB_A1, b));
     {
         Prof pr(ctx, BCG_K_CONVERT);
-        HIPCK(launch_canon_to_int((const double2*)in, Prec::FP64, W(ctx, WB_A0), nrhs, (int)ctx->Vh, ctx->stream));
+        HIPCK(launch_canon_to_int((const double2*)in, Wd(ctx, WB_A0), nrhs, (int)ctx->Vh, ctx->stream));
     }
     RETCK(hop(ctx, Prec::FP64, out_parity, W(ctx, WB_A0), W(ctx, WB_A1), nullptr, nrhs, EPI_PLAIN_, nullptr));
     Prof pr(ctx, BCG_K_CONVERT);
-    HIPCK(launch_int_to_canon(Prec::FP64, W(ctx, WB_A1), (double2*)out, nrhs, (int)ctx->Vh, ctx->stream));
+    HIPCK(launch_int_to_canon(Wd(ctx, WB_A1), (double2*)out, nrhs, (int)ctx->Vh, ctx->stream));
     return BCG_OK;
 }
 
@@ -466,8 +490,8 @@ int bcg_link_force(bcg_ctx* ctx, const void* X, const void* Lam, int nrhs, void*
     for (int s : {WB_A0, WB_A1, WB_A2, WB_A3}) RETCK(ensure(ctx, s, b));
     {
         Prof pr(ctx, BCG_K_CONVERT);
-        HIPCK(launch_canon_to_int((const double2*)X, Prec::FP64, W(ctx, WB_A0), nrhs, (int)ctx->Vh, ctx->stream));
-        HIPCK(launch_canon_to_int((const double2*)Lam, Prec::FP64, W(ctx, WB_A1), nrhs, (int)ctx->Vh, ctx->stream));
+        HIPCK(launch_canon_to_int((const double2*)X, Wd(ctx, WB_A0), nrhs, (int)ctx->Vh, ctx->stream));
+        HIPCK(launch_canon_to_int((const double2*)Lam, Wd(ctx, WB_A1), nrhs, (int)ctx->Vh, ctx->stream));
     }
     RETCK(hop(ctx, Prec::FP64, 1, W(ctx, WB_A0), W(ctx, WB_A2), nullptr, nrhs, EPI_PLAIN_, nullptr));
     RETCK(hop(ctx, Prec::FP64, 1, W(ctx, WB_A1), W(ctx, WB_A3), nullptr, nrhs, EPI_PLAIN_, nullptr));
@@ -507,7 +531,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
 
     {
         Prof pr(ctx, BCG_K_CONVERT);
-        HIPCK(launch_canon_to_int((const double2*)B, Prec::FP64, B64, N, Vh, s));
+        HIPCK(launch_canon_to_int((const double2*)B, B64, N, Vh, s));
     }
     RETCK(colnorms(ctx, B64, N, d_bnorm));
     HIPCK(hipMemcpyAsync(ctx->h_vec, d_bnorm, sizeof(double) * N, hipMemcpyDeviceToHost, s));
@@ -518,7 +542,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
 
     HIPCK(launch_zero(X, n * 16, s));
     if (use_guess) {
-        HIPCK(launch_canon_to_int((const double2*)Xout, Prec::FP64, Y, N, Vh, s));
+        HIPCK(launch_canon_to_int((const double2*)Xout, Y, N, Vh, s));
         RETCK(apply64(ctx, Y, R64, T64, N, nullptr));
         HIPCK(launch_residual(B64, R64, n, s));
     } else {
@@ -536,8 +560,16 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
     {
         Prof pr(ctx, BCG_K_OTHER);
         HIPCK(launch_bmul(Prec::FP64, R64, ps, nullptr, Qb[cur], M(ctx, M_CINV), N, Vh, halt, s));
-        HIPCK(launch_copy(Qb[cur], Pb[cur], n * (long)prec_bytes(ps), s));
+        HIPCK(launch_copy(Qb[cur], Pb[cur], (long)store_bytes(ps, N, 3, ctx->Vh), s));
     }
+    // fused path: G = 4 m^2 P^H P + T^H T, with P^H P kept as partials from the
+    // kernel that last wrote P (here the initial P = Q)
+    const bool fuse = fused_ok(ctx, ps, N);
+    const double m2 = 4.0 * ctx->mass * ctx->mass;
+    int n_pp = gram_parts(N, Vh);
+    const int n_tt = hop_grid(ctx->g, shape(ctx, N), true);
+    const int n_h = fused_grid(Vh);
+    if (fuse) RETCK(gram_partials(ctx, ps, Pb[cur], Pb[cur], N, ctx->part_pp, halt));
     RETCK(read_state(ctx));
     int status = BCG_OK;
     int n_ru = 0;
@@ -571,18 +603,32 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
         int c = cur;
         for (int k = 0; k < chunk; ++k) {
             void *P = Pb[c], *Q = Qb[c], *Pn = Pb[1 - c], *Qn = Qb[1 - c];
-            RETCK(hop(ctx, ps, 1, P, T, nullptr, N, EPI_PLAIN_, halt));
-            RETCK(hop(ctx, ps, 0, T, AP, P, N, EPI_MASS_, halt));
-            RETCK(gram(ctx, ps, P, AP, N, M(ctx, M_G), halt));
+            if (fuse) {
+                RETCK(hop(ctx, ps, 1, P, T, nullptr, N, EPI_PLAIN_, halt, nullptr, ctx->part_tt));
+                RETCK(hop(ctx, ps, 0, T, AP, P, N, EPI_MASS_, halt));
+                RETCK(reduce(ctx, ctx->part_tt, n_tt, ctx->part_pp, n_pp, m2, N, M(ctx, M_G), halt));
+            } else {
+                RETCK(hop(ctx, ps, 1, P, T, nullptr, N, EPI_PLAIN_, halt));
+                RETCK(hop(ctx, ps, 0, T, AP, P, N, EPI_MASS_, halt));
+                RETCK(gram(ctx, ps, P, AP, N, M(ctx, M_G), halt));
+            }
             {
                 Prof pr(ctx, BCG_K_SMALL);
                 HIPCK(launch_small1(M(ctx, M_G), M(ctx, M_C), M(ctx, M_BETA), M(ctx, M_BETAC), st, N, s));
             }
-            {
-                Prof pr(ctx, BCG_K_PASS_A);
-                HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, s));
+            if (fuse) {
+                {
+                    Prof pr(ctx, BCG_K_PASS_A);
+                    HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, ctx->partials, ctx->opt[BCG_OPT_PASS_CPT], s));
+                }
+                RETCK(reduce(ctx, ctx->partials, n_h, nullptr, 0, 0.0, N, M(ctx, M_H), halt));
+            } else {
+                {
+                    Prof pr(ctx, BCG_K_PASS_A);
+                    HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, nullptr, ctx->opt[BCG_OPT_PASS_CPT], s));
+                }
+                RETCK(gram(ctx, ps, Q, Q, N, M(ctx, M_H), halt));
             }
-            RETCK(gram(ctx, ps, Q, Q, N, M(ctx, M_H), halt));
             {
                 Prof pr(ctx, BCG_K_SMALL);
                 HIPCK(launch_small2(M(ctx, M_H), M(ctx, M_C), M(ctx, M_SINV), M(ctx, M_SH), st, N, s));
@@ -590,8 +636,9 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
             {
                 Prof pr(ctx, BCG_K_PASS_B);
                 HIPCK(launch_pass_b(ps, X, Q, P, Qn, Pn, M(ctx, M_BETAC), M(ctx, M_SINV), M(ctx, M_SH),
-                                    N, Vh, st, s));
+                                    N, Vh, st, fuse ? ctx->part_pp : nullptr, ctx->opt[BCG_OPT_PASS_CPT], s));
             }
+            n_pp = fused_grid(Vh);
             c = 1 - c;
         }
         RETCK(read_state(ctx));
@@ -640,6 +687,10 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
             HIPCK(launch_bmul(Prec::FP64, R64, ps, nullptr, Qb[1 - cur], M(ctx, M_CINV), N, Vh, ru_skip, s));
             HIPCK(launch_bmul(ps, Pb[cur], ps, Qb[1 - cur], Pb[1 - cur], M(ctx, M_SH), N, Vh, ru_skip, s));
         }
+        if (fuse) {
+            RETCK(gram_partials(ctx, ps, Pb[1 - cur], Pb[1 - cur], N, ctx->part_pp, ru_skip));
+            n_pp = gram_parts(N, Vh);
+        }
         RETCK(read_state(ctx));
         if (hs.reason == HALT_DONE) {
             finished = true;
@@ -671,7 +722,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
     }
     {
         Prof pr(ctx, BCG_K_CONVERT);
-        HIPCK(launch_int_to_canon(Prec::FP64, Y, (double2*)Xout, N, Vh, s));
+        HIPCK(launch_int_to_canon(Y, (double2*)Xout, N, Vh, s));
     }
     HIPCK(hipMemcpyAsync(ctx->h_vec, d_true, sizeof(double) * N, hipMemcpyDeviceToHost, s));
     HIPCK(hipMemcpyAsync(ctx->h_vec + MAXN, d_bnorm, sizeof(double) * N, hipMemcpyDeviceToHost, s));
@@ -714,7 +765,7 @@ int bcg_solve_cg(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, bcg_stats* s
     double* d_true = ctx->d_vec + MAXN;
     {
         Prof pr(ctx, BCG_K_CONVERT);
-        HIPCK(launch_canon_to_int((const double2*)B, Prec::FP64, B64, N, Vh, s));
+        HIPCK(launch_canon_to_int((const double2*)B, B64, N, Vh, s));
     }
     RETCK(colnorms(ctx, B64, N, ctx->d_vec));
     HIPCK(hipMemcpyAsync(ctx->h_vec, ctx->d_vec, sizeof(double) * N, hipMemcpyDeviceToHost, s));
@@ -797,12 +848,19 @@ int bcg_solve_cg(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, bcg_stats* s
     }
     {
         Prof pr(ctx, BCG_K_CONVERT);
-        HIPCK(launch_int_to_canon(Prec::FP64, Xs, (double2*)Xout, N, Vh, s));
+        HIPCK(launch_int_to_canon(Xs, (double2*)Xout, N, Vh, s));
     }
     RETCK(sync(ctx));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_stats(stats, total_iters, 0, status, restarts, secs, tr, N);
     return status;
+}
+
+int bcg_set_option(bcg_ctx* ctx, int option, int value) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (option < 0 || option >= BCG_OPT_COUNT) return fail(ctx, BCG_ERR_ARG, "unknown option");
+    ctx->opt[option] = value;
+    return BCG_OK;
 }
 
 int bcg_set_profiling(bcg_ctx* ctx, unsigned mask) {

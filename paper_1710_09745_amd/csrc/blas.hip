@@ -13,12 +13,23 @@
 // rows of both block vectors in LDS and accumulate register blocks of the N x N
 // result in FP64; partial results per workgroup are summed in a fixed order by
 // a second kernel, so every reduction is deterministic.
+#include <cstdlib>
+#include <type_traits>
+
 #include "device_common.h"
+#include "gram_tile.h"
 #include "internal.h"
+#include "storage.h"
 
 namespace bcg {
 
 template <typename T> using PairT = typename Store<T>::pair;
+
+// scale array of a [cols][K][Vh] block allocation in policy S (nullptr if unscaled)
+template <typename S> static inline float* scale_of(const void* p, long cols, int K, long Vh) {
+    if (!S::scaled || p == nullptr) return nullptr;
+    return (float*)((char*)p + (size_t)S::bytes * cols * K * Vh);
+}
 
 template <typename P> __device__ __forceinline__ C2<double> ldd(const P* p) {
     const P v = *p;
@@ -47,125 +58,82 @@ template <> struct GramCfg<16> { static constexpr int S = 32, RB = 4; };
 template <> struct GramCfg<32> { static constexpr int S = 16, RB = 4; };
 template <> struct GramCfg<64> { static constexpr int S = 8, RB = 4; };
 
-template <typename T, int NB>
+template <typename S, int NB>
 __global__ void __launch_bounds__(256)
-k_gram(const PairT<T>* __restrict__ A, const PairT<T>* __restrict__ B, int N, int Vh,
+k_gram(const typename S::pair* __restrict__ A, const float* __restrict__ As_,
+       const typename S::pair* __restrict__ B, const float* __restrict__ Bs_, int N, int Vh,
        double2* __restrict__ partials, const int* __restrict__ halt) {
     if (halt != nullptr && *halt) return;
-    constexpr int S = GramCfg<NB>::S, RB = GramCfg<NB>::RB;
-    constexpr int R = 3 * S, LD = NB + 1;
-    constexpr int NBB = NB / RB, NBLK = NBB * NBB, G = 256 / NBLK;
+    constexpr int SITES = GramCfg<NB>::S;
+    constexpr int R = 3 * SITES, LD = NB + 1;
+    constexpr int EPT = (R * NB + 255) / 256;   // tile elements per thread
     __shared__ C2<double> As[R * LD];
     __shared__ C2<double> Bs[R * LD];
     const bool same = (A == B);
     const int t = threadIdx.x;
-    const int blk = t % NBLK, grp = t / NBLK;
-    const int bi = blk / NBB, bj = blk % NBB;
-    C2<double> acc[RB][RB];
-#pragma unroll
-    for (int m = 0; m < RB; ++m)
-#pragma unroll
-        for (int n = 0; n < RB; ++n) acc[m][n] = C2<double>{0.0, 0.0};
+    GramAcc<NB> acc;
+    acc.zero();
     for (int e = t; e < R * LD; e += 256) {
         As[e] = C2<double>{0.0, 0.0};
         Bs[e] = C2<double>{0.0, 0.0};
     }
-    const int ntiles = (Vh + S - 1) / S;
+    // the next tile is loaded into registers while the current one is reduced
+    C2<double> ra[EPT], rb[EPT];
+    auto fetch = [&](int tile) {
+        const int site0 = tile * SITES;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int e = t + 256 * k;
+            const int sidx = e % SITES, c = (e / SITES) % 3, j = e / R;
+            const int site = site0 + sidx;
+            ra[k] = C2<double>{0.0, 0.0};
+            rb[k] = C2<double>{0.0, 0.0};
+            if (j < N && site < Vh) {
+                ra[k] = load_one_d<S, 3>(A, As_, Vh, j, c, site);
+                if (!same) rb[k] = load_one_d<S, 3>(B, Bs_, Vh, j, c, site);
+            }
+        }
+    };
+    const int ntiles = (Vh + SITES - 1) / SITES;
+    if (blockIdx.x < ntiles) fetch(blockIdx.x);
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         __syncthreads();
-        const int site0 = tile * S;
-        for (int e = t; e < R * N; e += 256) {
-            const int s = e % S;
-            const int rest = e / S;
-            const int c = rest % 3;
-            const int j = rest / 3;
-            const int site = site0 + s;
-            C2<double> a{0.0, 0.0}, b{0.0, 0.0};
-            if (site < Vh) {
-                const long o = ((long)j * 3 + c) * Vh + site;
-                a = ldd(A + o);
-                if (!same) b = ldd(B + o);
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int e = t + 256 * k;
+            const int sidx = e % SITES, c = (e / SITES) % 3, j = e / R;
+            if (j < N) {
+                As[(c * SITES + sidx) * LD + j] = ra[k];
+                if (!same) Bs[(c * SITES + sidx) * LD + j] = rb[k];
             }
-            As[(c * S + s) * LD + j] = a;
-            if (!same) Bs[(c * S + s) * LD + j] = b;
         }
         __syncthreads();
-        const C2<double>* Bp = same ? As : Bs;
-        for (int r = grp; r < R; r += G) {
-            C2<double> a[RB], b[RB];
-#pragma unroll
-            for (int m = 0; m < RB; ++m) {
-                a[m] = As[r * LD + bi * RB + m];
-                b[m] = Bp[r * LD + bj * RB + m];
-            }
-#pragma unroll
-            for (int m = 0; m < RB; ++m)
-#pragma unroll
-                for (int n = 0; n < RB; ++n) cmac_conj(acc[m][n], a[m], b[n]);
-        }
+        if (tile + gridDim.x < ntiles) fetch(tile + gridDim.x);
+        gram_tile_acc<NB, double>(As, same ? As : Bs, R, acc);
     }
-    double2* out = partials + (long)blockIdx.x * NB * NB;
-    if (G == 1) {
-#pragma unroll
-        for (int m = 0; m < RB; ++m)
-#pragma unroll
-            for (int n = 0; n < RB; ++n)
-                out[(bi * RB + m) * NB + bj * RB + n] = make_double2(acc[m][n].re, acc[m][n].im);
-        return;
-    }
-    // lanes of one wave that share a register block: reduce them with shuffles
-    if (NBLK < 64) {
-#pragma unroll
-        for (int off = NBLK; off < 64; off <<= 1)
-#pragma unroll
-            for (int m = 0; m < RB; ++m)
-#pragma unroll
-                for (int n = 0; n < RB; ++n) {
-                    acc[m][n].re += __shfl_xor(acc[m][n].re, off, 64);
-                    acc[m][n].im += __shfl_xor(acc[m][n].im, off, 64);
-                }
-    }
-    // then the four waves, in order, through LDS
-    __syncthreads();
-    C2<double>* red = As;
-    const int wave = t >> 6, lane = t & 63;
-    const bool holder = (NBLK >= 64) || (lane < NBLK);
-    for (int w = 0; w < 4; ++w) {
-        if (wave == w && holder) {
-#pragma unroll
-            for (int m = 0; m < RB; ++m)
-#pragma unroll
-                for (int n = 0; n < RB; ++n) {
-                    const int idx = (bi * RB + m) * NB + bj * RB + n;
-                    if (w == 0) red[idx] = acc[m][n];
-                    else {
-                        red[idx].re += acc[m][n].re;
-                        red[idx].im += acc[m][n].im;
-                    }
-                }
-        }
-        __syncthreads();
-    }
-    for (int e = t; e < NB * NB; e += 256) out[e] = make_double2(red[e].re, red[e].im);
+    gram_finish<NB>(acc, As, partials + (long)blockIdx.x * NB * NB);
 }
 
-template <typename T>
+template <typename S>
 static void gram_t(const void* A, const void* B, int N, int Vh, double2* partials, const int* halt,
                    hipStream_t s, int nb) {
-    auto go = [&](auto kern, int S) {
-        const int ntiles = (Vh + S - 1) / S;
+    using P = typename S::pair;
+    float* as = scale_of<S>(A, N, 3, Vh);
+    float* bs = scale_of<S>(B, N, 3, Vh);
+    auto go = [&](auto kern, int sites) {
+        const int ntiles = (Vh + sites - 1) / sites;
         const int grid = ntiles < GRAM_BLOCKS ? ntiles : GRAM_BLOCKS;
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, (const PairT<T>*)A, (const PairT<T>*)B,
-                           N, Vh, partials, halt);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, (const P*)A, as, (const P*)B, bs, N, Vh,
+                           partials, halt);
     };
     switch (nb) {
-        case 1: go(k_gram<T, 1>, GramCfg<1>::S); break;
-        case 2: go(k_gram<T, 2>, GramCfg<2>::S); break;
-        case 4: go(k_gram<T, 4>, GramCfg<4>::S); break;
-        case 8: go(k_gram<T, 8>, GramCfg<8>::S); break;
-        case 16: go(k_gram<T, 16>, GramCfg<16>::S); break;
-        case 32: go(k_gram<T, 32>, GramCfg<32>::S); break;
-        default: go(k_gram<T, 64>, GramCfg<64>::S); break;
+        case 1: go(k_gram<S, 1>, GramCfg<1>::S); break;
+        case 2: go(k_gram<S, 2>, GramCfg<2>::S); break;
+        case 4: go(k_gram<S, 4>, GramCfg<4>::S); break;
+        case 8: go(k_gram<S, 8>, GramCfg<8>::S); break;
+        case 16: go(k_gram<S, 16>, GramCfg<16>::S); break;
+        case 32: go(k_gram<S, 32>, GramCfg<32>::S); break;
+        default: go(k_gram<S, 64>, GramCfg<64>::S); break;
     }
 }
 
@@ -187,239 +155,423 @@ static int gram_nparts(int Vh, int nb) {
 hipError_t launch_gram(Prec prec, const void* A, const void* B, int N, int Vh, double2* partials,
                        const int* halt, hipStream_t s) {
     const int nb = pad_n(N);
-    if (prec == Prec::FP64) gram_t<double>(A, B, N, Vh, partials, halt, s, nb);
-    else if (prec == Prec::FP32) gram_t<float>(A, B, N, Vh, partials, halt, s, nb);
-    else return hipErrorInvalidValue;
+    switch (prec) {
+        case Prec::FP64: gram_t<F64>(A, B, N, Vh, partials, halt, s, nb); break;
+        case Prec::FP32: gram_t<F32>(A, B, N, Vh, partials, halt, s, nb); break;
+        case Prec::FP16: gram_t<H16>(A, B, N, Vh, partials, halt, s, nb); break;
+        case Prec::BF16: gram_t<B16>(A, B, N, Vh, partials, halt, s, nb); break;
+    }
     return hipGetLastError();
 }
 
-// out[i*64 + j] = sum_b partials[b][i*NB + j], b = 0, 1, ... in order
-__global__ void __launch_bounds__(1024)
-k_gram_reduce(const double2* __restrict__ partials, int NB, int N, int P, double2* __restrict__ out,
-              const int* __restrict__ halt) {
-    if (halt != nullptr && *halt) return;
-    __shared__ double2 red[16][64];
-    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-    const int e = blockIdx.x * 64 + lane;
-    const int NN = NB * NB;
-    double sr = 0.0, si = 0.0;
-    if (e < NN)
-        for (int p = grp; p < P; p += 16) {
-            const double2 v = partials[(long)p * NN + e];
-            sr += v.x;
-            si += v.y;
+int gram_parts(int N, int Vh) { return gram_nparts(Vh, pad_n(N)); }
+
+// out[i*64 + j] = sum_b pa[b][e] + alpha * sum_b pb[b][e], e = i*NB + j, in a fixed
+// order: 8 entries per workgroup, 32 lanes per entry each summing every 32nd
+// partial (16 independent loads in flight per lane), then the 32 lane totals.
+__device__ __forceinline__ void partial_sum(const double2* __restrict__ part, int P, int NN, int e,
+                                            int lane, double& sr, double& si) {
+    for (int p0 = lane; p0 < P; p0 += 32 * 16) {
+        double2 v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int p = p0 + 32 * u;
+            v[u] = p < P ? part[(long)p * NN + e] : make_double2(0.0, 0.0);
         }
-    red[grp][lane] = make_double2(sr, si);
-    __syncthreads();
-    if (grp == 0 && e < NN) {
-        double tr = 0.0, ti = 0.0;
-        for (int g = 0; g < 16; ++g) {
-            tr += red[g][lane].x;
-            ti += red[g][lane].y;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            sr += v[u].x;
+            si += v[u].y;
         }
-        const int i = e / NB, j = e % NB;
-        if (i < N && j < N) out[i * MAXN + j] = make_double2(tr, ti);
     }
 }
 
-hipError_t launch_gram_reduce(const double2* partials, int N, int Vh, double2* out,
-                              const int* halt, hipStream_t s) {
-    const int nb = pad_n(N);
-    const int grid = (nb * nb + 63) / 64;
-    hipLaunchKernelGGL(k_gram_reduce, dim3(grid), dim3(1024), 0, s, partials, nb, N,
-                       gram_nparts(Vh, nb), out, halt);
+__global__ void __launch_bounds__(256)
+k_gram_reduce(const double2* __restrict__ pa, int na, const double2* __restrict__ pb, int nb,
+              double alpha, int NB, int N, double2* __restrict__ out, const int* __restrict__ halt) {
+    if (halt != nullptr && *halt) return;
+    __shared__ double2 red[2][8][33];
+    const int ent = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    const int e = blockIdx.x * 8 + ent;
+    const int NN = NB * NB;
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+    if (e < NN) {
+        partial_sum(pa, na, NN, e, lane, ar, ai);
+        if (pb != nullptr) partial_sum(pb, nb, NN, e, lane, br, bi);
+    }
+    red[0][ent][lane] = make_double2(ar, ai);
+    red[1][ent][lane] = make_double2(br, bi);
+    __syncthreads();
+    if (lane == 0 && e < NN) {
+        double tr = 0.0, ti = 0.0, ur = 0.0, ui = 0.0;
+        for (int g = 0; g < 32; ++g) {
+            tr += red[0][ent][g].x;
+            ti += red[0][ent][g].y;
+            ur += red[1][ent][g].x;
+            ui += red[1][ent][g].y;
+        }
+        const int i = e / NB, j = e % NB;
+        if (i < N && j < N) out[i * MAXN + j] = make_double2(tr + alpha * ur, ti + alpha * ui);
+    }
+}
+
+hipError_t launch_gram_reduce(const double2* pa, int na, const double2* pb, int nb, double alpha, int N,
+                              double2* out, const int* halt, hipStream_t s) {
+    const int NBv = pad_n(N);
+    const int grid = (NBv * NBv + 7) / 8;
+    hipLaunchKernelGGL(k_gram_reduce, dim3(grid), dim3(256), 0, s, pa, na, pb, nb, alpha, NBv, N, out, halt);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------------
-// Pass A:  Q <- Q - AP beta   (Alg. 1: Q S = Q - A P beta, before its QR)
+// Fused Gram epilogues.  A workgroup owns 64 consecutive sites (one per lane) and
+// all N columns; with GR the kernel is persistent over such site tiles, stages
+// the block it produces (3 colours x 64 sites = 192 rows, NB columns) in LDS and
+// accumulates its Gram there (gram_tile.h), writing one NB x NB partial per
+// workgroup.  Without GR it is one tile per workgroup and no LDS.
 // ---------------------------------------------------------------------------------------------
-template <typename T, int CPT>
+template <typename S, int NB> struct FusedTile {
+    using E = typename TileElem<S>::type;
+    static constexpr int ROWS = 192;
+    static constexpr size_t bytes = (size_t)ROWS * (NB + 1) * sizeof(C2<E>);
+};
+
+// LDS bytes a fused epilogue of precision prec and block size N would need, or 0
+// when it does not fit the 64 KB budget this build allows per workgroup.
+size_t fused_tile_bytes(Prec prec, int N) {
+    const int nb = pad_n(N);
+    const size_t e = (prec == Prec::FP64) ? 16 : 8;
+    const size_t b = (size_t)192 * (nb + 1) * e;
+    return b <= 65536 ? b : 0;
+}
+
+int fused_grid(int Vh) {
+    const int nsb = (Vh + 63) / 64;
+    return nsb < GRAM_BLOCKS ? nsb : GRAM_BLOCKS;
+}
+
+template <typename E, typename R>
+__device__ __forceinline__ void tile_put(C2<E>* tile, int NBp1, int lane, int j, const C2<R> v[3], bool valid) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        tile[(c * 64 + lane) * NBp1 + j] = valid ? C2<E>{(E)v[c].re, (E)v[c].im} : C2<E>{(E)0, (E)0};
+}
+
+// ---------------------------------------------------------------------------------------------
+// Pass A:  Q <- Q - AP beta   (Alg. 1: Q S = Q - A P beta, before its QR);
+// with GR also the partials of H = Qt^H Qt (Alg. 2 on Qt).
+// ---------------------------------------------------------------------------------------------
+template <typename S, int CPT, int NB, bool GR>
 __global__ void __launch_bounds__(256)
-k_pass_a(PairT<T>* __restrict__ Q, const PairT<T>* __restrict__ AP, const double2* __restrict__ beta,
-         int N, int Vh, const int* __restrict__ halt) {
-    using R = typename Store<T>::real;
+k_pass_a(typename S::pair* __restrict__ Q, float* __restrict__ Qs, const typename S::pair* __restrict__ AP,
+         const float* __restrict__ APs, const double2* __restrict__ beta, int N, int Vh,
+         const int* __restrict__ halt, double2* __restrict__ partials) {
+    using R = typename S::real;
+    using E = typename TileElem<S>::type;
+    extern __shared__ unsigned char lds_raw[];
+    C2<E>* tile = reinterpret_cast<C2<E>*>(lds_raw);
     if (halt != nullptr && *halt) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + lane;
-    if (i >= Vh) return;
-    for (int j0 = wave * CPT; j0 < N; j0 += 4 * CPT) {
-        C2<R> acc[CPT][3];
+    const int nsb = (Vh + 63) / 64;
+    GramAcc<NB> acc;
+    if constexpr (GR) {
+        acc.zero();
+        for (int e = threadIdx.x; e < FusedTile<S, NB>::ROWS * (NB + 1); e += 256)
+            tile[e] = C2<E>{(E)0, (E)0};
+    }
+    for (int sb = blockIdx.x; sb < nsb; sb += gridDim.x) {
+        const int i = sb * 64 + lane;
+        const bool valid = i < Vh;
+        if constexpr (GR) __syncthreads();
+        for (int j0 = wave * CPT; j0 < N; j0 += 4 * CPT) {
+            C2<R> acc2[CPT][3];
 #pragma unroll
-        for (int m = 0; m < CPT; ++m)
+            for (int m = 0; m < CPT; ++m)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc[m][c] = C2<R>{0, 0};
-        for (int l = 0; l < N; ++l) {
-            C2<R> a[3];
+                for (int c = 0; c < 3; ++c) acc2[m][c] = C2<R>{0, 0};
+            if (valid) {
+#pragma unroll 4
+                for (int l = 0; l < N; ++l) {
+                    C2<R> a[3];
+                    load_group<S, 3>(AP, APs, Vh, l, i, a);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) a[c] = ld(AP + ((long)l * 3 + c) * Vh + i);
+                    for (int m = 0; m < CPT; ++m) {
+                        if (j0 + m < N) {
+                            const double2 bd = beta[l * MAXN + j0 + m];
+                            const C2<R> b{(R)bd.x, (R)bd.y};
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) cmac(acc2[m][c], a[c], b);
+                        }
+                    }
+                }
+            }
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
                 if (j0 + m < N) {
-                    const double2 bd = beta[l * MAXN + j0 + m];
-                    const C2<R> b{(R)bd.x, (R)bd.y};
+                    C2<R> q[3] = {C2<R>{0, 0}, C2<R>{0, 0}, C2<R>{0, 0}};
+                    if (valid) {
+                        load_group<S, 3>(Q, Qs, Vh, j0 + m, i, q);
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) cmac(acc[m][c], a[c], b);
+                        for (int c = 0; c < 3; ++c) {
+                            q[c].re -= acc2[m][c].re;
+                            q[c].im -= acc2[m][c].im;
+                        }
+                        store_group_rt<S, 3, R>(Q, Qs, Vh, j0 + m, i, q);
+                    }
+                    if constexpr (GR) tile_put<E, R>(tile, NB + 1, lane, j0 + m, q, valid);
                 }
             }
         }
-#pragma unroll
-        for (int m = 0; m < CPT; ++m) {
-            if (j0 + m < N) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    PairT<T>* q = Q + ((long)(j0 + m) * 3 + c) * Vh + i;
-                    C2<R> v = ld(q);
-                    v.re -= acc[m][c].re;
-                    v.im -= acc[m][c].im;
-                    st(q, v);
-                }
-            }
+        if constexpr (GR) {
+            __syncthreads();
+            gram_tile_acc<NB, E>(tile, tile, FusedTile<S, NB>::ROWS, acc);
         }
+    }
+    if constexpr (GR) gram_finish<NB>(acc, reinterpret_cast<C2<double>*>(lds_raw), partials + (long)blockIdx.x * NB * NB);
+}
+
+// columns per thread of the streaming passes (cpt_req 1, 2 or 4 overrides the default 4)
+static int pass_cpt(int N, int cpt_req) {
+    const int c = (cpt_req == 1 || cpt_req == 2 || cpt_req == 4) ? cpt_req : 4;
+    return N < c ? (N == 1 ? 1 : (N == 2 ? 2 : c)) : c;
+}
+
+template <typename S, int CPT, int NB, bool GR>
+static void pass_a_go(void* Q, const void* AP, const double2* beta, int N, int Vh, const int* halt,
+                      double2* partials, hipStream_t s) {
+    using P = typename S::pair;
+    const int grid = GR ? fused_grid(Vh) : (Vh + 63) / 64;
+    const size_t lds = GR ? FusedTile<S, NB>::bytes : 0;
+    hipLaunchKernelGGL((k_pass_a<S, CPT, NB, GR>), dim3(grid), dim3(256), lds, s, (P*)Q, scale_of<S>(Q, N, 3, Vh),
+                       (const P*)AP, scale_of<S>(AP, N, 3, Vh), beta, N, Vh, halt, partials);
+}
+
+template <typename S, int CPT>
+static void pass_a_nb(void* Q, const void* AP, const double2* beta, int N, int Vh, const int* halt,
+                      double2* partials, hipStream_t s) {
+    if (partials == nullptr) return pass_a_go<S, CPT, 1, false>(Q, AP, beta, N, Vh, halt, nullptr, s);
+    switch (pad_n(N)) {
+        case 1: return pass_a_go<S, CPT, 1, true>(Q, AP, beta, N, Vh, halt, partials, s);
+        case 2: return pass_a_go<S, CPT, 2, true>(Q, AP, beta, N, Vh, halt, partials, s);
+        case 4: return pass_a_go<S, CPT, 4, true>(Q, AP, beta, N, Vh, halt, partials, s);
+        case 8: return pass_a_go<S, CPT, 8, true>(Q, AP, beta, N, Vh, halt, partials, s);
+        case 16: return pass_a_go<S, CPT, 16, true>(Q, AP, beta, N, Vh, halt, partials, s);
+        default:
+            if constexpr (!std::is_same<S, F64>::value) return pass_a_go<S, CPT, 32, true>(Q, AP, beta, N, Vh, halt, partials, s);
     }
 }
 
+template <typename S>
+static void pass_a_t(void* Q, const void* AP, const double2* beta, int N, int Vh, const int* halt,
+                     double2* partials, int cpt_req, hipStream_t s) {
+    const int cpt = pass_cpt(N, cpt_req);
+    if (cpt == 1) pass_a_nb<S, 1>(Q, AP, beta, N, Vh, halt, partials, s);
+    else if (cpt == 2) pass_a_nb<S, 2>(Q, AP, beta, N, Vh, halt, partials, s);
+    else pass_a_nb<S, 4>(Q, AP, beta, N, Vh, halt, partials, s);
+}
+
 hipError_t launch_pass_a(Prec prec, void* Q, const void* AP, const double2* beta, int N, int Vh,
-                         const int* halt, hipStream_t s) {
-    dim3 grid((Vh + 63) / 64);
-    if (prec == Prec::FP64) {
-        if (N == 1) hipLaunchKernelGGL((k_pass_a<double, 1>), grid, dim3(256), 0, s, (double2*)Q, (const double2*)AP, beta, N, Vh, halt);
-        else if (N == 2) hipLaunchKernelGGL((k_pass_a<double, 2>), grid, dim3(256), 0, s, (double2*)Q, (const double2*)AP, beta, N, Vh, halt);
-        else hipLaunchKernelGGL((k_pass_a<double, 4>), grid, dim3(256), 0, s, (double2*)Q, (const double2*)AP, beta, N, Vh, halt);
-    } else if (prec == Prec::FP32) {
-        if (N == 1) hipLaunchKernelGGL((k_pass_a<float, 1>), grid, dim3(256), 0, s, (float2*)Q, (const float2*)AP, beta, N, Vh, halt);
-        else if (N == 2) hipLaunchKernelGGL((k_pass_a<float, 2>), grid, dim3(256), 0, s, (float2*)Q, (const float2*)AP, beta, N, Vh, halt);
-        else hipLaunchKernelGGL((k_pass_a<float, 4>), grid, dim3(256), 0, s, (float2*)Q, (const float2*)AP, beta, N, Vh, halt);
-    } else {
-        return hipErrorInvalidValue;
+                         const int* halt, double2* partials, int cpt, hipStream_t s) {
+    if (partials != nullptr && fused_tile_bytes(prec, N) == 0) return hipErrorInvalidValue;
+    switch (prec) {
+        case Prec::FP64: pass_a_t<F64>(Q, AP, beta, N, Vh, halt, partials, cpt, s); break;
+        case Prec::FP32: pass_a_t<F32>(Q, AP, beta, N, Vh, halt, partials, cpt, s); break;
+        case Prec::FP16: pass_a_t<H16>(Q, AP, beta, N, Vh, halt, partials, cpt, s); break;
+        case Prec::BF16: pass_a_t<B16>(Q, AP, beta, N, Vh, halt, partials, cpt, s); break;
     }
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------------
 // Pass B (Alg. 1, with the X update of the same iteration deferred to here, Sec. 6.2):
-//   X  += P (beta C)                      (old P)
+//   X  += P (beta C)                      (old P; formed and added in FP64)
 //   Qn  = Qt S^{-1}                       (S^{-1} upper triangular: l <= j only)
 //   Pn  = Qn + P S^H                      (S^H lower triangular: l >= j only)
 // Qn, Pn are written to other buffers than Qt, P (ping-pong), so there is no
 // in-place hazard between the waves that read all columns and those that write.
+// With GR also the partials of Pn^H Pn (the P^H P term of the next iteration's
+// G = 4 m^2 P^H P + T^H T).
 // ---------------------------------------------------------------------------------------------
-template <typename T, int CPT>
+template <typename S, int CPT, int NB, bool GR>
 __global__ void __launch_bounds__(256)
-k_pass_b(double2* __restrict__ X, const PairT<T>* __restrict__ Qt, const PairT<T>* __restrict__ P,
-         PairT<T>* __restrict__ Qn, PairT<T>* __restrict__ Pn, const double2* __restrict__ betaC,
-         const double2* __restrict__ Sinv, const double2* __restrict__ SH, int N, int Vh,
-         const SolveState* __restrict__ stt) {
-    using R = typename Store<T>::real;
+k_pass_b(double2* __restrict__ X, const typename S::pair* __restrict__ Qt, const float* __restrict__ Qts,
+         const typename S::pair* __restrict__ P, const float* __restrict__ Ps,
+         typename S::pair* __restrict__ Qn, float* __restrict__ Qns, typename S::pair* __restrict__ Pn,
+         float* __restrict__ Pns, const double2* __restrict__ betaC, const double2* __restrict__ Sinv,
+         const double2* __restrict__ SH, int N, int Vh, const SolveState* __restrict__ stt,
+         double2* __restrict__ partials) {
+    using R = typename S::real;
+    using E = typename TileElem<S>::type;
+    extern __shared__ unsigned char lds_raw[];
+    C2<E>* tile = reinterpret_cast<C2<E>*>(lds_raw);
     const int mode = stt->pb_mode;
     if (mode == PB_SKIP) return;
     const bool full = (mode == PB_FULL);
+    const bool gram = GR && full;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + lane;
-    if (i >= Vh) return;
-    for (int j0 = wave * CPT; j0 < N; j0 += 4 * CPT) {
-        C2<double> xa[CPT][3];
-        C2<R> qa[CPT][3], pa[CPT][3];
+    const int nsb = (Vh + 63) / 64;
+    GramAcc<NB> acc;
+    if constexpr (GR) {
+        acc.zero();
+        for (int e = threadIdx.x; e < FusedTile<S, NB>::ROWS * (NB + 1); e += 256)
+            tile[e] = C2<E>{(E)0, (E)0};
+    }
+    for (int sb = blockIdx.x; sb < nsb; sb += gridDim.x) {
+        const int i = sb * 64 + lane;
+        const bool valid = i < Vh;
+        if (gram) __syncthreads();
+        for (int j0 = wave * CPT; j0 < N; j0 += 4 * CPT) {
+            C2<double> xa[CPT][3];
+            C2<R> qa[CPT][3], pa[CPT][3];
 #pragma unroll
-        for (int m = 0; m < CPT; ++m)
+            for (int m = 0; m < CPT; ++m)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                xa[m][c] = C2<double>{0.0, 0.0};
-                qa[m][c] = C2<R>{0, 0};
-                pa[m][c] = C2<R>{0, 0};
+                for (int c = 0; c < 3; ++c) {
+                    xa[m][c] = C2<double>{0.0, 0.0};
+                    qa[m][c] = C2<R>{0, 0};
+                    pa[m][c] = C2<R>{0, 0};
+                }
+            if (valid) {
+#pragma unroll 4
+                for (int l = 0; l < N; ++l) {
+                    C2<R> p[3];
+                    load_group<S, 3>(P, Ps, Vh, l, i, p);
+#pragma unroll
+                    for (int m = 0; m < CPT; ++m) {
+                        if (j0 + m < N) {
+                            const double2 bc = betaC[l * MAXN + j0 + m];
+#pragma unroll
+                            for (int c = 0; c < 3; ++c)
+                                cmac(xa[m][c], C2<double>{(double)p[c].re, (double)p[c].im}, C2<double>{bc.x, bc.y});
+                        }
+                    }
+                    if (full) {
+                        if (l >= j0) {
+#pragma unroll
+                            for (int m = 0; m < CPT; ++m) {
+                                if (j0 + m < N && l >= j0 + m) {
+                                    const double2 sh = SH[l * MAXN + j0 + m];
+                                    const C2<R> b{(R)sh.x, (R)sh.y};
+#pragma unroll
+                                    for (int c = 0; c < 3; ++c) cmac(pa[m][c], p[c], b);
+                                }
+                            }
+                        }
+                        if (l < j0 + CPT) {
+                            C2<R> q[3];
+                            load_group<S, 3>(Qt, Qts, Vh, l, i, q);
+#pragma unroll
+                            for (int m = 0; m < CPT; ++m) {
+                                if (j0 + m < N && l <= j0 + m) {
+                                    const double2 si = Sinv[l * MAXN + j0 + m];
+                                    const C2<R> b{(R)si.x, (R)si.y};
+#pragma unroll
+                                    for (int c = 0; c < 3; ++c) cmac(qa[m][c], q[c], b);
+                                }
+                            }
+                        }
+                    }
+                }
             }
-        for (int l = 0; l < N; ++l) {
-            C2<R> p[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) p[c] = ld(P + ((long)l * 3 + c) * Vh + i);
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
                 if (j0 + m < N) {
-                    const double2 bc = betaC[l * MAXN + j0 + m];
+                    if (valid) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        cmac(xa[m][c], C2<double>{(double)p[c].re, (double)p[c].im}, C2<double>{bc.x, bc.y});
-                }
-            }
-            if (full) {
-                if (l >= j0) {
-#pragma unroll
-                    for (int m = 0; m < CPT; ++m) {
-                        if (j0 + m < N && l >= j0 + m) {
-                            const double2 sh = SH[l * MAXN + j0 + m];
-                            const C2<R> b{(R)sh.x, (R)sh.y};
-#pragma unroll
-                            for (int c = 0; c < 3; ++c) cmac(pa[m][c], p[c], b);
+                        for (int c = 0; c < 3; ++c) {
+                            const long o = ((long)(j0 + m) * 3 + c) * Vh + i;
+                            double2 xv = X[o];
+                            xv.x += xa[m][c].re;
+                            xv.y += xa[m][c].im;
+                            X[o] = xv;
                         }
                     }
-                }
-                if (l < j0 + CPT) {
-                    C2<R> q[3];
+                    if (full) {
+                        if (valid) {
+                            store_group<S, 3, R>(Qn, Qns, Vh, j0 + m, i, qa[m]);
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) q[c] = ld(Qt + ((long)l * 3 + c) * Vh + i);
-#pragma unroll
-                    for (int m = 0; m < CPT; ++m) {
-                        if (j0 + m < N && l <= j0 + m) {
-                            const double2 si = Sinv[l * MAXN + j0 + m];
-                            const C2<R> b{(R)si.x, (R)si.y};
-#pragma unroll
-                            for (int c = 0; c < 3; ++c) cmac(qa[m][c], q[c], b);
+                            for (int c = 0; c < 3; ++c) {
+                                pa[m][c].re += qa[m][c].re;
+                                pa[m][c].im += qa[m][c].im;
+                            }
+                            store_group_rt<S, 3, R>(Pn, Pns, Vh, j0 + m, i, pa[m]);
                         }
+                        if constexpr (GR) tile_put<E, R>(tile, NB + 1, lane, j0 + m, pa[m], valid);
                     }
                 }
             }
         }
-#pragma unroll
-        for (int m = 0; m < CPT; ++m) {
-            if (j0 + m < N) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const long o = ((long)(j0 + m) * 3 + c) * Vh + i;
-                    double2 xv = X[o];
-                    xv.x += xa[m][c].re;
-                    xv.y += xa[m][c].im;
-                    X[o] = xv;
-                    if (full) {
-                        st(Qn + o, qa[m][c]);
-                        C2<R> pv{qa[m][c].re + pa[m][c].re, qa[m][c].im + pa[m][c].im};
-                        st(Pn + o, pv);
-                    }
-                }
-            }
+        if (gram) {
+            __syncthreads();
+            gram_tile_acc<NB, E>(tile, tile, FusedTile<S, NB>::ROWS, acc);
         }
     }
+    if (gram) gram_finish<NB>(acc, reinterpret_cast<C2<double>*>(lds_raw), partials + (long)blockIdx.x * NB * NB);
+}
+
+template <typename S, int CPT, int NB, bool GR>
+static void pass_b_go(double2* X, const void* Qt, const void* P, void* Qn, void* Pn, const double2* betaC,
+                      const double2* Sinv, const double2* SH, int N, int Vh, const SolveState* st,
+                      double2* partials, hipStream_t s) {
+    using PP = typename S::pair;
+    const int grid = GR ? fused_grid(Vh) : (Vh + 63) / 64;
+    const size_t lds = GR ? FusedTile<S, NB>::bytes : 0;
+    hipLaunchKernelGGL((k_pass_b<S, CPT, NB, GR>), dim3(grid), dim3(256), lds, s, X, (const PP*)Qt,
+                       scale_of<S>(Qt, N, 3, Vh), (const PP*)P, scale_of<S>(P, N, 3, Vh), (PP*)Qn,
+                       scale_of<S>(Qn, N, 3, Vh), (PP*)Pn, scale_of<S>(Pn, N, 3, Vh), betaC, Sinv, SH, N, Vh,
+                       st, partials);
+}
+
+template <typename S, int CPT>
+static void pass_b_nb(double2* X, const void* Qt, const void* P, void* Qn, void* Pn, const double2* betaC,
+                      const double2* Sinv, const double2* SH, int N, int Vh, const SolveState* st,
+                      double2* partials, hipStream_t s) {
+#define PBG(NBV, GRV) pass_b_go<S, CPT, NBV, GRV>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, s)
+    if (partials == nullptr) return PBG(1, false);
+    switch (pad_n(N)) {
+        case 1: return PBG(1, true);
+        case 2: return PBG(2, true);
+        case 4: return PBG(4, true);
+        case 8: return PBG(8, true);
+        case 16: return PBG(16, true);
+        default:
+            if constexpr (!std::is_same<S, F64>::value) return PBG(32, true);
+    }
+#undef PBG
+}
+
+template <typename S>
+static void pass_b_t(double2* X, const void* Qt, const void* P, void* Qn, void* Pn, const double2* betaC,
+                     const double2* Sinv, const double2* SH, int N, int Vh, const SolveState* st,
+                     double2* partials, int cpt_req, hipStream_t s) {
+    const int cpt = pass_cpt(N, cpt_req);
+    if (cpt == 1) pass_b_nb<S, 1>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, s);
+    else if (cpt == 2) pass_b_nb<S, 2>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, s);
+    else pass_b_nb<S, 4>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, s);
 }
 
 hipError_t launch_pass_b(Prec prec, double2* X, const void* Qt, const void* P, void* Qn, void* Pn,
                          const double2* betaC, const double2* Sinv, const double2* SH, int N,
-                         int Vh, const SolveState* state, hipStream_t s) {
-    dim3 grid((Vh + 63) / 64);
-#define PB_LAUNCH(TT, CC)                                                                             \
-    hipLaunchKernelGGL((k_pass_b<TT, CC>), grid, dim3(256), 0, s, X, (const PairT<TT>*)Qt,           \
-                       (const PairT<TT>*)P, (PairT<TT>*)Qn, (PairT<TT>*)Pn, betaC, Sinv, SH, N, Vh, \
-                       state)
-    if (prec == Prec::FP64) {
-        if (N == 1) PB_LAUNCH(double, 1);
-        else if (N == 2) PB_LAUNCH(double, 2);
-        else PB_LAUNCH(double, 4);
-    } else if (prec == Prec::FP32) {
-        if (N == 1) PB_LAUNCH(float, 1);
-        else if (N == 2) PB_LAUNCH(float, 2);
-        else PB_LAUNCH(float, 4);
-    } else {
-        return hipErrorInvalidValue;
+                         int Vh, const SolveState* state, double2* partials, int cpt, hipStream_t s) {
+    if (partials != nullptr && fused_tile_bytes(prec, N) == 0) return hipErrorInvalidValue;
+    switch (prec) {
+        case Prec::FP64: pass_b_t<F64>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, s); break;
+        case Prec::FP32: pass_b_t<F32>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, s); break;
+        case Prec::FP16: pass_b_t<H16>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, s); break;
+        case Prec::BF16: pass_b_t<B16>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, s); break;
     }
-#undef PB_LAUNCH
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------------
 // Y <- Z + X M   (block caxpy, Eq. 3), all buffers distinct; Z may be NULL.
 // ---------------------------------------------------------------------------------------------
-template <typename TX, typename TY, int CPT>
+template <typename SX, typename SY, int CPT>
 __global__ void __launch_bounds__(256)
-k_bmul(const PairT<TX>* __restrict__ X, const PairT<TY>* __restrict__ Z, PairT<TY>* __restrict__ Y,
-       const double2* __restrict__ M, int N, int Vh, const int* __restrict__ skip) {
+k_bmul(const typename SX::pair* __restrict__ X, const float* __restrict__ Xs,
+       const typename SY::pair* __restrict__ Z, const float* __restrict__ Zs,
+       typename SY::pair* __restrict__ Y, float* __restrict__ Ys, const double2* __restrict__ M, int N,
+       int Vh, const int* __restrict__ skip) {
     if (skip != nullptr && *skip) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + lane;
@@ -430,128 +582,106 @@ k_bmul(const PairT<TX>* __restrict__ X, const PairT<TY>* __restrict__ Z, PairT<T
         for (int m = 0; m < CPT; ++m)
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[m][c] = C2<double>{0.0, 0.0};
+#pragma unroll 4
         for (int l = 0; l < N; ++l) {
-            C2<double> a[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) a[c] = ldd(X + ((long)l * 3 + c) * Vh + i);
+            C2<typename SX::real> a[3];
+            load_group<SX, 3>(X, Xs, Vh, l, i, a);
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
                 if (j0 + m < N) {
                     const C2<double> b = dld(M + l * MAXN + j0 + m);
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) cmac(acc[m][c], a[c], b);
+                    for (int c = 0; c < 3; ++c)
+                        cmac(acc[m][c], C2<double>{(double)a[c].re, (double)a[c].im}, b);
                 }
             }
         }
 #pragma unroll
         for (int m = 0; m < CPT; ++m) {
             if (j0 + m < N) {
+                if (Z != nullptr) {
+                    C2<typename SY::real> z[3];
+                    load_group<SY, 3>(Z, Zs, Vh, j0 + m, i, z);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const long o = ((long)(j0 + m) * 3 + c) * Vh + i;
-                    C2<double> v = acc[m][c];
-                    if (Z != nullptr) {
-                        const C2<double> z = ldd(Z + o);
-                        v.re += z.re;
-                        v.im += z.im;
+                    for (int c = 0; c < 3; ++c) {
+                        acc[m][c].re += (double)z[c].re;
+                        acc[m][c].im += (double)z[c].im;
                     }
-                    st(Y + o, v);
                 }
+                store_group<SY, 3, double>(Y, Ys, Vh, j0 + m, i, acc[m]);
             }
         }
     }
 }
 
+template <typename SX, typename SY>
+static void bmul_t(const void* X, const void* Z, void* Y, const double2* M, int N, int Vh, const int* skip,
+                   hipStream_t s) {
+    dim3 grid((Vh + 63) / 64);
+    hipLaunchKernelGGL((k_bmul<SX, SY, 4>), grid, dim3(256), 0, s, (const typename SX::pair*)X,
+                       scale_of<SX>(X, N, 3, Vh), (const typename SY::pair*)Z, scale_of<SY>(Z, N, 3, Vh),
+                       (typename SY::pair*)Y, scale_of<SY>(Y, N, 3, Vh), M, N, Vh, skip);
+}
+
+template <typename SX>
+static hipError_t bmul_y(Prec py, const void* X, const void* Z, void* Y, const double2* M, int N, int Vh,
+                         const int* skip, hipStream_t s) {
+    switch (py) {
+        case Prec::FP64: bmul_t<SX, F64>(X, Z, Y, M, N, Vh, skip, s); break;
+        case Prec::FP32: bmul_t<SX, F32>(X, Z, Y, M, N, Vh, skip, s); break;
+        case Prec::FP16: bmul_t<SX, H16>(X, Z, Y, M, N, Vh, skip, s); break;
+        case Prec::BF16: bmul_t<SX, B16>(X, Z, Y, M, N, Vh, skip, s); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_bmul(Prec px, const void* X, Prec py, const void* Z, void* Y, const double2* M,
                        int N, int Vh, const int* skip, hipStream_t s) {
-    dim3 grid((Vh + 63) / 64);
-#define BM_LAUNCH(TX, TY)                                                                          \
-    hipLaunchKernelGGL((k_bmul<TX, TY, 4>), grid, dim3(256), 0, s, (const PairT<TX>*)X,           \
-                       (const PairT<TY>*)Z, (PairT<TY>*)Y, M, N, Vh, skip)
-    if (px == Prec::FP64 && py == Prec::FP64) BM_LAUNCH(double, double);
-    else if (px == Prec::FP64 && py == Prec::FP32) BM_LAUNCH(double, float);
-    else if (px == Prec::FP32 && py == Prec::FP32) BM_LAUNCH(float, float);
-    else if (px == Prec::FP32 && py == Prec::FP64) BM_LAUNCH(float, double);
-    else return hipErrorInvalidValue;
-#undef BM_LAUNCH
-    return hipGetLastError();
+    switch (px) {
+        case Prec::FP64: return bmul_y<F64>(py, X, Z, Y, M, N, Vh, skip, s);
+        case Prec::FP32: return bmul_y<F32>(py, X, Z, Y, M, N, Vh, skip, s);
+        case Prec::FP16: return bmul_y<H16>(py, X, Z, Y, M, N, Vh, skip, s);
+        case Prec::BF16: return bmul_y<B16>(py, X, Z, Y, M, N, Vh, skip, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------------------------
 // Layout conversion and small vector kernels
 // ---------------------------------------------------------------------------------------------
-template <typename T>
 __global__ void __launch_bounds__(256)
-k_canon_to_int(const double2* __restrict__ src, PairT<T>* __restrict__ dst, int N, long Vh) {
+k_canon_to_int(const double2* __restrict__ src, double2* __restrict__ dst, int N, long Vh) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long)N * Vh) return;
     const long n = t / Vh, i = t - n * Vh;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double2 v = src[t * 3 + c];
-        PairT<T> w;
-        w.x = (T)v.x;
-        w.y = (T)v.y;
-        dst[(n * 3 + c) * Vh + i] = w;
-    }
+    for (int c = 0; c < 3; ++c) dst[(n * 3 + c) * Vh + i] = src[t * 3 + c];
 }
 
-template <typename T>
 __global__ void __launch_bounds__(256)
-k_int_to_canon(const PairT<T>* __restrict__ src, double2* __restrict__ dst, int N, long Vh) {
+k_int_to_canon(const double2* __restrict__ src, double2* __restrict__ dst, int N, long Vh) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long)N * Vh) return;
     const long n = t / Vh, i = t - n * Vh;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const PairT<T> v = src[(n * 3 + c) * Vh + i];
-        dst[t * 3 + c] = make_double2((double)v.x, (double)v.y);
-    }
+    for (int c = 0; c < 3; ++c) dst[t * 3 + c] = src[(n * 3 + c) * Vh + i];
 }
 
-hipError_t launch_canon_to_int(const double2* src, Prec pd, void* dst, int N, int Vh, hipStream_t s) {
+hipError_t launch_canon_to_int(const double2* src, double2* dst, int N, int Vh, hipStream_t s) {
     const long n = (long)N * Vh;
-    dim3 grid((unsigned)((n + 255) / 256));
-    if (pd == Prec::FP64) hipLaunchKernelGGL(k_canon_to_int<double>, grid, dim3(256), 0, s, src, (double2*)dst, N, (long)Vh);
-    else if (pd == Prec::FP32) hipLaunchKernelGGL(k_canon_to_int<float>, grid, dim3(256), 0, s, src, (float2*)dst, N, (long)Vh);
-    else return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_canon_to_int, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, N, (long)Vh);
     return hipGetLastError();
 }
 
-hipError_t launch_int_to_canon(Prec ps, const void* src, double2* dst, int N, int Vh, hipStream_t s) {
+hipError_t launch_int_to_canon(const double2* src, double2* dst, int N, int Vh, hipStream_t s) {
     const long n = (long)N * Vh;
-    dim3 grid((unsigned)((n + 255) / 256));
-    if (ps == Prec::FP64) hipLaunchKernelGGL(k_int_to_canon<double>, grid, dim3(256), 0, s, (const double2*)src, dst, N, (long)Vh);
-    else if (ps == Prec::FP32) hipLaunchKernelGGL(k_int_to_canon<float>, grid, dim3(256), 0, s, (const float2*)src, dst, N, (long)Vh);
-    else return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_int_to_canon, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, N, (long)Vh);
     return hipGetLastError();
-}
-
-template <typename TS, typename TD>
-__global__ void __launch_bounds__(256)
-k_convert(const PairT<TS>* __restrict__ src, PairT<TD>* __restrict__ dst, long n) {
-    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-        const PairT<TS> v = src[t];
-        PairT<TD> w;
-        w.x = (TD)v.x;
-        w.y = (TD)v.y;
-        dst[t] = w;
-    }
 }
 
 static unsigned stream_grid(long n) {
     long g = (n + 255) / 256;
     return (unsigned)(g < 4096 ? (g > 0 ? g : 1) : 4096);
-}
-
-hipError_t launch_convert(Prec ps, const void* src, Prec pd, void* dst, long n, hipStream_t s) {
-    const dim3 grid(stream_grid(n));
-    if (ps == Prec::FP64 && pd == Prec::FP32) hipLaunchKernelGGL((k_convert<double, float>), grid, dim3(256), 0, s, (const double2*)src, (float2*)dst, n);
-    else if (ps == Prec::FP32 && pd == Prec::FP64) hipLaunchKernelGGL((k_convert<float, double>), grid, dim3(256), 0, s, (const float2*)src, (double2*)dst, n);
-    else if (ps == Prec::FP64 && pd == Prec::FP64) hipLaunchKernelGGL((k_convert<double, double>), grid, dim3(256), 0, s, (const double2*)src, (double2*)dst, n);
-    else if (ps == Prec::FP32 && pd == Prec::FP32) hipLaunchKernelGGL((k_convert<float, float>), grid, dim3(256), 0, s, (const float2*)src, (float2*)dst, n);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
 }
 
 __global__ void __launch_bounds__(256) k_fold_x(double2* __restrict__ Y, double2* __restrict__ X, long n) {

@@ -15,8 +15,24 @@ constexpr int NORM_BLOCKS = 512;  // workgroups of a column-norm reduction
 
 struct HopShape {
     int tr;   // right-hand sides per lane (register tile)
-    int tpb;  // right-hand-side tiles per workgroup (cache tile)
+    int tpb;  // lane groups per workgroup sharing the same sites (cache tile)
+    int pf;   // 1: software-pipelined link loop
 };
+
+// bytes per stored complex number, and bytes of a [cols][K][Vh] allocation
+// including the per-group FP32 scales of the 16-bit formats
+inline int pd_bytes(Prec p) {
+    switch (p) {
+        case Prec::FP64: return 16;
+        case Prec::FP32: return 8;
+        default: return 4;
+    }
+}
+inline size_t store_bytes(Prec p, long cols, int K, long Vh) {
+    size_t b = (size_t)pd_bytes(p) * cols * K * Vh;
+    if (p == Prec::FP16 || p == Prec::BF16) b += (size_t)4 * cols * Vh;
+    return b;
+}
 
 // padded block size used to instantiate the N-dependent kernels: 1, 2, 4, ..., 64
 inline int pad_n(int n) {
@@ -26,13 +42,20 @@ inline int pad_n(int n) {
 }
 
 // hop.hip ---------------------------------------------------------------------------------------
-hipError_t pack_links(Prec prec, const void* fat, const void* lng, void* W, const Geom& g,
-                      int parity, int nl, hipStream_t s);
-HopShape hop_shape(int N);
+// FP64 folded links of one output parity from canonical device links
+hipError_t pack_links(const void* fat, const void* lng, void* W, const Geom& g, int parity, int nl,
+                      hipStream_t s);
+// lower-precision folded links from the FP64 ones
+hipError_t links_from64(Prec pd, const void* W64, void* Wd, int nl, long Vh, hipStream_t s);
+HopShape hop_shape(int N, int tr = 0, int tpb = 0, int pf = 0);
 int hop_dot_blocks(const Geom& g);
+// partials != nullptr (EPI_PLAIN only): also T^H T partials of the output, one per
+// workgroup of the persistent grid hop_grid(g, h, true)
 hipError_t launch_hop(Prec prec, int nl, const void* W, const void* in, void* out, const void* ctr,
                       double m2, int N, const Geom& g, int out_parity, int epi, const HopShape& h,
-                      const int* halt, double* dot, hipStream_t s);
+                      const int* halt, double* dot, double2* partials, hipStream_t s);
+size_t hop_tile_bytes(Prec prec, int N, const HopShape& h);
+int hop_grid(const Geom& g, const HopShape& h, bool fused);
 enum { EPI_PLAIN_ = 0, EPI_MASS_ = 1, EPI_MASS_DOT_ = 2 };
 
 // blas.hip --------------------------------------------------------------------------------------
@@ -40,23 +63,28 @@ enum { EPI_PLAIN_ = 0, EPI_MASS_ = 1, EPI_MASS_DOT_ = 2 };
 hipError_t launch_gram(Prec prec, const void* A, const void* B, int N, int Vh, double2* partials,
                        const int* halt, hipStream_t s);
 // out[i*64 + j] = sum_b partials[b][i*NB + j]  (fixed order)
-hipError_t launch_gram_reduce(const double2* partials, int N, int Vh, double2* out,
-                              const int* halt, hipStream_t s);
-// Q <- Q - AP beta    (beta: [64][64] FP64)
+// number of partials launch_gram writes
+int gram_parts(int N, int Vh);
+// out[i*64 + j] = sum_b pa[b][i*NB + j] + alpha * sum_b pb[b][i*NB + j]  (fixed order; pb may be NULL)
+hipError_t launch_gram_reduce(const double2* pa, int na, const double2* pb, int nb, double alpha, int N,
+                              double2* out, const int* halt, hipStream_t s);
+// LDS bytes of a fused Gram epilogue of the streaming passes (0: does not fit, use launch_gram)
+size_t fused_tile_bytes(Prec prec, int N);
+int fused_grid(int Vh);
+// Q <- Q - AP beta    (beta: [64][64] FP64); partials != nullptr: also Qt^H Qt partials
 hipError_t launch_pass_a(Prec prec, void* Q, const void* AP, const double2* beta, int N, int Vh,
-                         const int* halt, hipStream_t s);
-// X += P betaC; Qn <- Qt Sinv; Pn <- Qn + P S^H, as selected by state->pb_mode
+                         const int* halt, double2* partials, int cpt, hipStream_t s);
+// X += P betaC; Qn <- Qt Sinv; Pn <- Qn + P S^H, as selected by state->pb_mode;
+// partials != nullptr: also Pn^H Pn partials
 hipError_t launch_pass_b(Prec prec, double2* X, const void* Qt, const void* P, void* Qn, void* Pn,
                          const double2* betaC, const double2* Sinv, const double2* SH, int N,
-                         int Vh, const SolveState* state, hipStream_t s);
+                         int Vh, const SolveState* state, double2* partials, int cpt, hipStream_t s);
 // Y <- Z + X M  (Z may be NULL = 0; X, Z may alias Y); X in precision px, Y/Z in py
 hipError_t launch_bmul(Prec px, const void* X, Prec py, const void* Z, void* Y, const double2* M,
                        int N, int Vh, const int* skip, hipStream_t s);
-// canonical [N][Vh][3] complex128 <-> internal [N][3][Vh] pairs
-hipError_t launch_canon_to_int(const double2* src, Prec pd, void* dst, int N, int Vh, hipStream_t s);
-hipError_t launch_int_to_canon(Prec ps, const void* src, double2* dst, int N, int Vh, hipStream_t s);
-// internal FP64 <-> sloppy copy (same layout)
-hipError_t launch_convert(Prec ps, const void* src, Prec pd, void* dst, long n, hipStream_t s);
+// canonical [N][Vh][3] complex128 <-> internal FP64 [N][3][Vh] pairs
+hipError_t launch_canon_to_int(const double2* src, double2* dst, int N, int Vh, hipStream_t s);
+hipError_t launch_int_to_canon(const double2* src, double2* dst, int N, int Vh, hipStream_t s);
 // Y += X; X = 0 (FP64)
 hipError_t launch_fold_x(double2* Y, double2* X, long n, hipStream_t s);
 // R <- B - R (FP64)

@@ -35,71 +35,32 @@ __device__ void load_herm(Z2* A, const double2* M, int N) {
         const Z2 a = gld(M + i * MAXN + j), b = gld(M + j * MAXN + i);
         A[e] = Z2{0.5 * (a.re + b.re), 0.5 * (a.im - b.im)};
     }
-    __syncthreads();
+}
+
+// leading N x N block of a global [64][64] matrix into LDS (ld = N)
+__device__ void load_mat(Z2* A, const double2* M, int N) {
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) A[e] = gld(M + (e / N) * MAXN + e % N);
 }
 
 // In-place lower Cholesky A = L L^H (L with positive real diagonal, strict upper
-// triangle zeroed).  A pivot that is not positive or not finite is a breakdown:
-// returns false on every thread.
-__device__ bool chol_lower(Z2* A, int N, int* flag) {
-    if (threadIdx.x == 0) *flag = 0;
+// triangle zeroed), two barriers per column.  A pivot d_k that is not positive,
+// not finite, or (when diag != nullptr) not above 1e-14 of the column's own
+// original diagonal is a breakdown: returns false on every thread.  Every
+// thread reads the same pivot after a barrier, so the decision is uniform.
+__device__ bool chol_lower(Z2* A, int N, const double* diag) {
     __syncthreads();
     for (int k = 0; k < N; ++k) {
-        if (threadIdx.x == 0) {
-            const double d = A[k * N + k].re;
-            if (!(d > 0.0) || !isfinite(d)) *flag = 1;
-            else A[k * N + k] = Z2{sqrt(d), 0.0};
-        }
-        __syncthreads();
-        if (*flag) return false;
-        const double piv = A[k * N + k].re;
+        const double d = A[k * N + k].re;
+        const double floor_k = diag ? 1e-14 * diag[k] : 0.0;
+        if (!(d > floor_k) || !isfinite(d)) return false;
+        const double rs = 1.0 / sqrt(d);
         for (int i = k + 1 + threadIdx.x; i < N; i += blockDim.x) {
             const Z2 v = A[i * N + k];
-            A[i * N + k] = Z2{v.re / piv, v.im / piv};
+            A[i * N + k] = Z2{v.re * rs, v.im * rs};
         }
         __syncthreads();
         const int m = N - k - 1;
-        for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-            const int i = k + 1 + e / m, j = k + 1 + e % m;
-            if (j <= i) {
-                const Z2 lik = A[i * N + k], ljk = A[j * N + k];
-                const Z2 p = zmul(lik, zconj(ljk));
-                A[i * N + j].re -= p.re;
-                A[i * N + j].im -= p.im;
-            }
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
-        if (j > i) A[e] = Z2{0.0, 0.0};
-    }
-    __syncthreads();
-    return true;
-}
-
-// Relative pivot test: d_k / H_kk below 1e-14 means column k is numerically in
-// the span of the columns before it.  diag: the original diagonal (length N).
-__device__ bool chol_lower_checked(Z2* A, int N, int* flag, double* diag) {
-    for (int k = threadIdx.x; k < N; k += blockDim.x) diag[k] = A[k * N + k].re;
-    __syncthreads();
-    if (threadIdx.x == 0) *flag = 0;
-    __syncthreads();
-    for (int k = 0; k < N; ++k) {
-        if (threadIdx.x == 0) {
-            const double d = A[k * N + k].re;
-            if (!(d > 1e-14 * diag[k]) || !isfinite(d)) *flag = 1;
-            else A[k * N + k] = Z2{sqrt(d), 0.0};
-        }
-        __syncthreads();
-        if (*flag) return false;
-        const double piv = A[k * N + k].re;
-        for (int i = k + 1 + threadIdx.x; i < N; i += blockDim.x) {
-            const Z2 v = A[i * N + k];
-            A[i * N + k] = Z2{v.re / piv, v.im / piv};
-        }
-        __syncthreads();
-        const int m = N - k - 1;
+        if (threadIdx.x == 0) A[k * N + k] = Z2{d * rs, 0.0};
         for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
             const int i = k + 1 + e / m, j = k + 1 + e % m;
             if (j <= i) {
@@ -110,16 +71,14 @@ __device__ bool chol_lower_checked(Z2* A, int N, int* flag, double* diag) {
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
-        if (j > i) A[e] = Z2{0.0, 0.0};
-    }
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x)
+        if (e % N > e / N) A[e] = Z2{0.0, 0.0};
     __syncthreads();
     return true;
 }
 
-// Z = L^{-1} for lower-triangular L with real positive diagonal (column-oriented
-// elimination on the identity).
+// Z = L^{-1} for lower-triangular L with real positive diagonal, column by column
+// (two barriers per column, all updates of a column in parallel).
 __device__ void tri_inv_lower(const Z2* L, Z2* Zm, int N) {
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
         const int i = e / N, j = e % N;
@@ -141,6 +100,114 @@ __device__ void tri_inv_lower(const Z2* L, Z2* Zm, int N) {
             Zm[i * N + j].im -= p.im;
         }
         __syncthreads();
+    }
+}
+
+// Cholesky A = L L^H (in place, lower) and Z = L^{-1} together: step k scales
+// column k of L and row k of Z (phase 1), then updates the trailing block of A and
+// the rows below k of Z (phase 2); two barriers per column.  Same breakdown rule
+// as chol_lower.
+__device__ bool chol_inv_lower(Z2* A, Z2* Zm, int N, const double* diag) {
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int i = e / N, j = e % N;
+        Zm[e] = Z2{i == j ? 1.0 : 0.0, 0.0};
+    }
+    __syncthreads();
+    for (int k = 0; k < N; ++k) {
+        const double d = A[k * N + k].re;
+        const double floor_k = diag ? 1e-14 * diag[k] : 0.0;
+        if (!(d > floor_k) || !isfinite(d)) return false;
+        const double rs = 1.0 / sqrt(d);
+        // phase 1: L[i][k] = A[i][k] / sqrt(d) (i > k);  Z[k][j] /= L[k][k] (j <= k)
+        for (int e = threadIdx.x; e < N; e += blockDim.x) {
+            if (e > k) {
+                const Z2 v = A[e * N + k];
+                A[e * N + k] = Z2{v.re * rs, v.im * rs};
+            } else {
+                const Z2 v = Zm[k * N + e];
+                Zm[k * N + e] = Z2{v.re * rs, v.im * rs};
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) A[k * N + k] = Z2{d * rs, 0.0};
+        // phase 2: trailing update of A (j <= i, both > k) and Z[i][j] -= L[i][k] Z[k][j]
+        const int m = N - k - 1;
+        for (int e = threadIdx.x; e < m * m + m * (k + 1); e += blockDim.x) {
+            if (e < m * m) {
+                const int i = k + 1 + e / m, j = k + 1 + e % m;
+                if (j <= i) {
+                    const Z2 p = zmul(A[i * N + k], zconj(A[j * N + k]));
+                    A[i * N + j].re -= p.re;
+                    A[i * N + j].im -= p.im;
+                }
+            } else {
+                const int f = e - m * m;
+                const int i = k + 1 + f / (k + 1), j = f % (k + 1);
+                const Z2 p = zmul(A[i * N + k], Zm[k * N + j]);
+                Zm[i * N + j].re -= p.re;
+                Zm[i * N + j].im -= p.im;
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x)
+        if (e % N > e / N) A[e] = Z2{0.0, 0.0};
+    __syncthreads();
+    return true;
+}
+
+// In-place Gauss-Jordan inverse of a Hermitian positive-definite A (no pivoting
+// needed: the pivots are the Cholesky pivots d_k > 0).  rowk, colk: LDS scratch of
+// length N.  Returns false on a non-positive pivot.
+__device__ bool gj_inverse_hpd(Z2* A, int N, Z2* rowk, Z2* colk) {
+    __syncthreads();
+    for (int k = 0; k < N; ++k) {
+        const double p = A[k * N + k].re;
+        if (!(p > 0.0) || !isfinite(p)) return false;
+        const double pinv = 1.0 / p;
+        for (int j = threadIdx.x; j < N; j += blockDim.x) {
+            const Z2 v = (j == k) ? Z2{1.0, 0.0} : A[k * N + j];
+            rowk[j] = Z2{v.re * pinv, v.im * pinv};
+            colk[j] = (j == k) ? Z2{0.0, 0.0} : A[j * N + k];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+            const int i = e / N, j = e % N;
+            if (i == k) {
+                A[e] = rowk[j];
+            } else {
+                const Z2 base = (j == k) ? Z2{0.0, 0.0} : A[e];
+                const Z2 q = zmul(colk[i], rowk[j]);
+                A[e] = Z2{base.re - q.re, base.im - q.im};
+            }
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// relres[i] = sqrt((C^H H C)_ii) / bnorm[i].  A group of G lanes (G = 16, 32 or
+// 64, the smallest power of two >= N) handles one column i, lane m forming
+// conj(C[m][i]) (H C)[m][i]; the group sums its lanes with shuffles.
+__device__ void residual_norms(const Z2* H, const Z2* C, int N, const double* bnorm, double* rel) {
+    const int G = N <= 16 ? 16 : (N <= 32 ? 32 : 64);
+    const int groups = blockDim.x / G;
+    const int m = threadIdx.x % G, grp = threadIdx.x / G;
+    for (int i0 = 0; i0 < N; i0 += groups) {
+        const int i = i0 + grp;
+        double t = 0.0;
+        if (i < N && m <= i) {   // C upper: C[m][i] = 0 for m > i, C[n][i] = 0 for n > i
+            Z2 hc{0.0, 0.0};
+            for (int n = 0; n <= i; ++n) {
+                const Z2 q = zmul(H[m * N + n], C[n * N + i]);
+                hc.re += q.re;
+                hc.im += q.im;
+            }
+            const Z2 c = C[m * N + i];
+            t = c.re * hc.re + c.im * hc.im;
+        }
+        for (int off = G >> 1; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (m == 0 && i < N) rel[i] = sqrt(fmax(t, 0.0)) / bnorm[i];
     }
 }
 
@@ -178,11 +245,12 @@ k_small_init(const double2* __restrict__ H, double2* __restrict__ C, double2* __
     extern __shared__ Z2 sm[];
     Z2* A = sm;
     Z2* Zm = sm + N * N;
-    __shared__ int flag;
     __shared__ double diag[MAXN];
     __shared__ double rel[MAXN];
     load_herm(A, H, N);
-    if (!chol_lower_checked(A, N, &flag, diag)) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < N; k += blockDim.x) diag[k] = A[k * N + k].re;
+    if (!chol_inv_lower(A, Zm, N, diag)) {
         if (threadIdx.x == 0) {
             st->halt = 1;
             st->reason = HALT_BREAKDOWN_H;
@@ -190,25 +258,19 @@ k_small_init(const double2* __restrict__ H, double2* __restrict__ C, double2* __
         }
         return;
     }
-    tri_inv_lower(A, Zm, N);
-    for (int e = threadIdx.x; e < MAXN * MAXN; e += blockDim.x) {
-        const int i = e / MAXN, j = e % MAXN;
-        Z2 c{0.0, 0.0}, ci{0.0, 0.0};
-        if (i < N && j < N && j >= i) {
-            c = zconj(A[j * N + i]);     // C = L^H
-            ci = zconj(Zm[j * N + i]);   // C^{-1} = (L^{-1})^H
-        }
-        gst(C + e, c);
-        gst(Cinv + e, ci);
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int i = e / N, j = e % N;
+        gst(C + i * MAXN + j, (j >= i) ? zconj(A[j * N + i]) : Z2{0.0, 0.0});      // C = L^H
+        gst(Cinv + i * MAXN + j, (j >= i) ? zconj(Zm[j * N + i]) : Z2{0.0, 0.0});  // C^{-1} = (L^{-1})^H
     }
     // relative residual of column i = ||C[:, i]|| / ||b_i||  (R = Q C)
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        double s = 0.0;
+        double s2 = 0.0;
         for (int m = 0; m <= i; ++m) {  // C[m][i] = conj(L[i][m]), nonzero for m <= i
             const Z2 v = A[i * N + m];
-            s += v.re * v.re + v.im * v.im;
+            s2 += v.re * v.re + v.im * v.im;
         }
-        rel[i] = sqrt(s) / st->bnorm[i];
+        rel[i] = sqrt(s2) / st->bnorm[i];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -225,42 +287,35 @@ k_small_init(const double2* __restrict__ H, double2* __restrict__ C, double2* __
     }
 }
 
-// beta = G^{-1} = L^{-H} L^{-1},  betaC = beta C
+// beta = G^{-1} (Gauss-Jordan on the Hermitian part of G), betaC = beta C
 __global__ void __launch_bounds__(1024)
 k_small1(const double2* __restrict__ G, const double2* __restrict__ C, double2* __restrict__ beta,
          double2* __restrict__ betaC, SolveState* st, int N) {
     if (st->halt) return;
     extern __shared__ Z2 sm[];
     Z2* A = sm;
-    Z2* Zm = sm + N * N;
-    __shared__ int flag;
+    Z2* Cm = sm + N * N;
+    __shared__ Z2 rowk[MAXN], colk[MAXN];
     load_herm(A, G, N);
-    if (!chol_lower(A, N, &flag)) {
+    load_mat(Cm, C, N);
+    if (!gj_inverse_hpd(A, N, rowk, colk)) {
         if (threadIdx.x == 0) {
             st->halt = 1;
             st->reason = HALT_BREAKDOWN_G;
         }
         return;
     }
-    tri_inv_lower(A, Zm, N);
-    // beta[i][j] = sum_m conj(Z[m][i]) Z[m][j], m >= max(i, j)
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
         const int i = e / N, j = e % N;
-        Z2 s{0.0, 0.0};
-        for (int m = (i > j ? i : j); m < N; ++m) {
-            const Z2 p = zmul(zconj(Zm[m * N + i]), Zm[m * N + j]);
-            s.re += p.re;
-            s.im += p.im;
-        }
-        A[e] = s;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
-        gst(beta + i * MAXN + j, A[e]);
+        // beta is Hermitian: average the two triangles the elimination produced
+        const Z2 a = A[e], b = A[j * N + i];
+        const Z2 bij{0.5 * (a.re + b.re), 0.5 * (a.im - b.im)};
+        gst(beta + i * MAXN + j, bij);
         Z2 s{0.0, 0.0};
         for (int m = 0; m <= j; ++m) {   // C upper triangular
-            const Z2 p = zmul(A[i * N + m], gld(C + m * MAXN + j));
+            const Z2 am = A[i * N + m], bm = A[m * N + i];
+            const Z2 bim{0.5 * (am.re + bm.re), 0.5 * (am.im - bm.im)};
+            const Z2 p = zmul(bim, Cm[m * N + j]);
             s.re += p.re;
             s.im += p.im;
         }
@@ -278,31 +333,12 @@ k_small2(const double2* __restrict__ H, double2* __restrict__ C, double2* __rest
     extern __shared__ Z2 sm[];
     Z2* A = sm;
     Z2* W = sm + N * N;
-    __shared__ int flag;
     __shared__ double rel[MAXN];
     __shared__ int decision;
     load_herm(A, H, N);
-    // W = H C
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
-        Z2 s{0.0, 0.0};
-        for (int m = 0; m <= j; ++m) {
-            const Z2 p = zmul(A[i * N + m], gld(C + m * MAXN + j));
-            s.re += p.re;
-            s.im += p.im;
-        }
-        W[e] = s;
-    }
+    load_mat(W, C, N);
     __syncthreads();
-    // ||r_i||^2 = (C^H H C)_ii = sum_m conj(C[m][i]) W[m][i]
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        double s = 0.0;
-        for (int m = 0; m <= i; ++m) {
-            const Z2 c = gld(C + m * MAXN + i), w = W[m * N + i];
-            s += c.re * w.re + c.im * w.im;
-        }
-        rel[i] = sqrt(fmax(s, 0.0)) / st->bnorm[i];
-    }
+    residual_norms(A, W, N, st->bnorm, rel);
     __syncthreads();
     if (threadIdx.x == 0) {
         double mx = 0.0;
@@ -323,7 +359,8 @@ k_small2(const double2* __restrict__ H, double2* __restrict__ C, double2* __rest
     }
     __syncthreads();
     if (decision != HALT_NONE) return;
-    if (!chol_lower(A, N, &flag)) {
+    // Cholesky of H and L^{-1} together (W, which held C, becomes L^{-1})
+    if (!chol_inv_lower(A, W, N, nullptr)) {
         if (threadIdx.x == 0) {
             st->halt = 1;
             st->reason = HALT_BREAKDOWN_H;
@@ -331,32 +368,29 @@ k_small2(const double2* __restrict__ H, double2* __restrict__ C, double2* __rest
         }
         return;
     }
-    tri_inv_lower(A, W, N);
-    // S = L^H; S^H = L; S^{-1} = (L^{-1})^H
-    for (int e = threadIdx.x; e < MAXN * MAXN; e += blockDim.x) {
-        const int i = e / MAXN, j = e % MAXN;
-        Z2 sh{0.0, 0.0}, si{0.0, 0.0};
-        if (i < N && j < N) {
-            if (j <= i) sh = A[i * N + j];
-            if (j >= i) si = zconj(W[j * N + i]);
-        }
-        gst(SH + e, sh);
-        gst(Sinv + e, si);
-    }
-    __syncthreads();
-    // C <- S C, S upper: (S C)[i][j] = sum_{m=i..j} conj(L[m][i]) C[m][j]
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+    // C <- S C with S = L^H upper: (S C)[i][j] = sum_{m=i..j} conj(L[m][i]) C[m][j];
+    // the old C is read from global memory, all reads finish before the writes
+    Z2 cn[4];   // N*N / blockDim <= 4 (N <= 16 with 256 threads, N <= 64 with 1024)
+    int cnt = 0;
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x, ++cnt) {
         const int i = e / N, j = e % N;
-        Z2 s{0.0, 0.0};
+        Z2 s2{0.0, 0.0};
         for (int m = i; m <= j; ++m) {
             const Z2 p = zmul(zconj(A[m * N + i]), gld(C + m * MAXN + j));
-            s.re += p.re;
-            s.im += p.im;
+            s2.re += p.re;
+            s2.im += p.im;
         }
-        W[e] = s;
+        cn[cnt] = s2;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) gst(C + (e / N) * MAXN + e % N, W[e]);
+    cnt = 0;
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x, ++cnt) gst(C + (e / N) * MAXN + e % N, cn[cnt]);
+    // S^H = L; S^{-1} = (L^{-1})^H  (leading N x N blocks only)
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int i = e / N, j = e % N;
+        gst(SH + i * MAXN + j, (j <= i) ? A[i * N + j] : Z2{0.0, 0.0});
+        gst(Sinv + i * MAXN + j, (j >= i) ? zconj(W[j * N + i]) : Z2{0.0, 0.0});
+    }
     if (threadIdx.x == 0) st->pb_mode = PB_FULL;
 }
 
@@ -368,7 +402,6 @@ k_small_ru(const double2* __restrict__ H, double2* __restrict__ C, double2* __re
     extern __shared__ Z2 sm[];
     Z2* A = sm;
     Z2* W = sm + N * N;
-    __shared__ int flag;
     __shared__ double diag[MAXN];
     __shared__ double rel[MAXN];
     __shared__ int done;
@@ -391,7 +424,9 @@ k_small_ru(const double2* __restrict__ H, double2* __restrict__ C, double2* __re
     __syncthreads();
     if (done) return;
     load_herm(A, H, N);
-    if (!chol_lower_checked(A, N, &flag, diag)) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < N; k += blockDim.x) diag[k] = A[k * N + k].re;
+    if (!chol_inv_lower(A, W, N, diag)) {
         if (threadIdx.x == 0) {
             st->halt = 1;
             st->reason = HALT_BREAKDOWN_H;
@@ -399,17 +434,11 @@ k_small_ru(const double2* __restrict__ H, double2* __restrict__ C, double2* __re
         }
         return;
     }
-    tri_inv_lower(A, W, N);
     // C^ = L^H -> temporarily in SH; C^{-1} = (L^{-1})^H -> Chinv
-    for (int e = threadIdx.x; e < MAXN * MAXN; e += blockDim.x) {
-        const int i = e / MAXN, j = e % MAXN;
-        Z2 c{0.0, 0.0}, ci{0.0, 0.0};
-        if (i < N && j < N && j >= i) {
-            c = zconj(A[j * N + i]);
-            ci = zconj(W[j * N + i]);
-        }
-        gst(SH + e, c);
-        gst(Chinv + e, ci);
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int i = e / N, j = e % N;
+        gst(SH + i * MAXN + j, (j >= i) ? zconj(A[j * N + i]) : Z2{0.0, 0.0});
+        gst(Chinv + i * MAXN + j, (j >= i) ? zconj(W[j * N + i]) : Z2{0.0, 0.0});
     }
     __syncthreads();
     // A <- C_k^H (lower), W <- (C_k^H)^{-1} = (C_k^{-1})^H
@@ -422,23 +451,24 @@ k_small_ru(const double2* __restrict__ H, double2* __restrict__ C, double2* __re
     // S^ = C^ C_k^{-1} (upper), C_k^{-1}[m][j] = conj(W[j][m])
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
         const int i = e / N, j = e % N;
-        Z2 s{0.0, 0.0};
+        Z2 s2{0.0, 0.0};
         for (int m = i; m <= j; ++m) {
             const Z2 p = zmul(gld(SH + i * MAXN + m), zconj(W[j * N + m]));
-            s.re += p.re;
-            s.im += p.im;
+            s2.re += p.re;
+            s2.im += p.im;
         }
-        A[e] = s;
+        A[e] = s2;
     }
     __syncthreads();
     // C <- C^ ; then S^H
-    for (int e = threadIdx.x; e < MAXN * MAXN; e += blockDim.x) C[e] = SH[e];
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int o = (e / N) * MAXN + e % N;
+        C[o] = SH[o];
+    }
     __syncthreads();
-    for (int e = threadIdx.x; e < MAXN * MAXN; e += blockDim.x) {
-        const int i = e / MAXN, j = e % MAXN;
-        Z2 v{0.0, 0.0};
-        if (i < N && j < N) v = zconj(A[j * N + i]);
-        gst(SH + e, v);
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int i = e / N, j = e % N;
+        gst(SH + i * MAXN + j, zconj(A[j * N + i]));
     }
     if (threadIdx.x == 0) {
         st->halt = 0;

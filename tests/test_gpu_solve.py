@@ -184,3 +184,79 @@ def test_config2_full_size_solve_and_cg():
     resc = true_rel_res(op, B[:2], Xc.cpu().numpy())
     print(f"config 2 cg (2 columns): iters={ic['iters']} t={ic['seconds']:.3f}s max res={resc.max():.2e}")
     assert resc.max() <= c["tol"]
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_mixed_16bit_reaches_tolerance(prec):
+    """16-bit storage with one FP32 scale per site and column (vectors) or per
+    folded link matrix, FP32 arithmetic, FP64 Gram / CholQR / reliable updates."""
+    dims = (8, 8, 8, 8)
+    fat, lng, B = inputs(dims, True, 8, 6600)
+    m = 0.1
+    c16 = context(dims, True, fat, lng, m, tol=1e-8, prec=prec, max_iter=20000)
+    X16, i16 = c16.solve(to_dev(B))
+    op = oracle.Operator(dims, fat, lng, m)
+    r16 = true_rel_res(op, B, X16.cpu().numpy())
+    c64 = context(dims, True, fat, lng, m, tol=1e-8, prec="fp64")
+    X64, i64 = c64.solve(to_dev(B))
+    d = np.linalg.norm((X16 - X64).cpu().numpy()) / np.linalg.norm(X64.cpu().numpy())
+    print(f"{prec}: iters={i16['iters']} rus={i16['reliable_updates']} (fp64 iters={i64['iters']}) "
+          f"max res={r16.max():.2e} ||X16-X64||/||X64||={d:.2e}")
+    assert r16.max() <= 1e-8
+    assert i16["reliable_updates"] >= 1
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_sloppy_iterates_track_fp64(prec):
+    """The first iterations in reduced storage stay close to the FP64 iterates
+    (error of the order of the storage precision times the small growth of a
+    few iterations)."""
+    dims = (6, 6, 6, 6)
+    fat, lng, B = inputs(dims, True, 4, 6700)
+    m = 0.2
+    eps = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}[prec]
+    c = context(dims, True, fat, lng, m, tol=1e-14, prec=prec, ru_delta=0.0, max_iter=3)
+    Xs, _ = c.solve(to_dev(B), raise_on_error=False)
+    op = oracle.Operator(dims, fat, lng, m)
+    Xo, _ = oracle.block_cg_rq(op.apply, B, 1e-14, max_iter=3)
+    err = col_rel_err(Xs.cpu().numpy(), Xo).max()
+    print(f"{prec}: 3-iteration error {err:.2e} (storage eps {eps:.1e})")
+    assert err <= 200 * eps
+
+
+@pytest.mark.parametrize("prec,n", [("fp64", 16), ("fp64", 5), ("fp32", 8), ("bf16", 3)])
+def test_fused_gram_path_matches_oracle(prec, n):
+    """Gram products fused into the hop and pass epilogues (G = 4 m^2 P^H P + T^H T)."""
+    dims = (8, 8, 6, 6)
+    fat, lng, B = inputs(dims, True, n, 6800 + n)
+    m = 0.1
+    tol = 1e-10 if prec == "fp64" else 1e-8
+    ctx = context(dims, True, fat, lng, m, tol=tol, prec=prec)
+    ctx.set_option("fuse_gram", 1)
+    X, info = ctx.solve(to_dev(B))
+    op = oracle.Operator(dims, fat, lng, m)
+    assert true_rel_res(op, B, X.cpu().numpy()).max() <= tol
+    if prec == "fp64":
+        ctx2 = context(dims, True, fat, lng, m, tol=1e-14, ru_delta=0.0, max_iter=4)
+        ctx2.set_option("fuse_gram", 1)
+        X4, _ = ctx2.solve(to_dev(B), raise_on_error=False)
+        Xo, _ = oracle.block_cg_rq(op.apply, B, 1e-14, max_iter=4)
+        assert col_rel_err(X4.cpu().numpy(), Xo).max() <= 1e-10
+
+
+@pytest.mark.parametrize("tr,tpb,pf,cpt", [(1, 4, 1, 1), (2, 2, 0, 2), (8, 1, 1, 4), (4, 4, 1, 2)])
+def test_launch_shapes_match_oracle(tr, tpb, pf, cpt):
+    """Every hop register tile / lane-group / pipelining choice and pass column
+    tile gives the same operator and iterates."""
+    dims = (6, 6, 6, 6)
+    n = 9
+    fat, lng, B = inputs(dims, True, n, 6900)
+    m = 0.15
+    ctx = context(dims, True, fat, lng, m, tol=1e-14, ru_delta=0.0, max_iter=3)
+    for name, v in [("hop_tr", tr), ("hop_tpb", tpb), ("hop_pipeline", pf), ("pass_cpt", cpt)]:
+        ctx.set_option(name, v)
+    op = oracle.Operator(dims, fat, lng, m)
+    assert col_rel_err(ctx.apply(to_dev(B)).cpu().numpy(), op.apply(B)).max() <= 1e-12
+    X3, _ = ctx.solve(to_dev(B), raise_on_error=False)
+    Xo, _ = oracle.block_cg_rq(op.apply, B, 1e-14, max_iter=3)
+    assert col_rel_err(X3.cpu().numpy(), Xo).max() <= 1e-10
