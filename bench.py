@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--nrhs", type=int, default=16)
     ap.add_argument("--prec", default=None, help="storage precision override (fp64/fp32/fp16/bf16)")
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device to device three times (the reference kernel for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to HBM bytes)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -119,12 +122,20 @@ def main():
         fat, lng, B = synth.config_inputs(3, nrhs=N)
     if args.prec:
         prec = args.prec
-    wkey = args.workload if args.workload == "config3" or prec != "fp64" else "config2"
+    wkey = f"{'x'.join(str(d) for d in dims)}_n{N}_{prec}"
     workload = (f"{'x'.join(str(d) for d in dims)} improved staggered (fat N(0,1)/3 + Haar long), "
                 f"m={m}, N={N}, {prec} storage{' + FP64 reliable updates' if prec != 'fp64' else ''}, "
                 f"tol {tol:g}")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        print("[bench] copy calibration: 3 x 1 GiB device copies", file=sys.stderr, flush=True)
     ctx = bcg.Context(dims, improved=True, device=dev)
     ctx.load_links(fat, lng)
     ctx.set_mass(m)
@@ -253,8 +264,9 @@ def cpu_baseline(dims, fat, lng, m, B, tol, gpu_iters, budget_s):
     est = per_iter * gpu_iters
     return {"value": round(est * 1e3 / N, 2), "unit": "ms/RHS", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"oracle blockCGrQ (C stencil + NumPy) on the same 16^4 N=16 input, first {k} "
-                      f"iterations in {t:.1f} s, extrapolated to the GPU's {gpu_iters} iterations"}
+            "sample": f"oracle blockCGrQ (C stencil + NumPy) on the same {'x'.join(str(d) for d in dims)} "
+                      f"N={N} input, first {k} iterations in {t:.1f} s, extrapolated to the GPU's "
+                      f"{gpu_iters} iterations"}
 
 
 if __name__ == "__main__":

@@ -155,13 +155,22 @@ int bcg_link_force(bcg_ctx *ctx, const void *X, const void *Lam, int nrhs, void 
  * them beyond floating-point rounding order).  value 0 restores the default.
  *   BCG_OPT_HOP_TR        right-hand sides per lane in the hop (1, 2, 4, 8)
  *   BCG_OPT_HOP_TPB       lane groups per workgroup sharing sites (1, 2, 4)
- *   BCG_OPT_HOP_PIPELINE  1: software-pipelined link loop in the hop
+ *   BCG_OPT_HOP_PIPELINE  1: two folded matrices in flight per loop trip, 2: one
  *   BCG_OPT_PASS_CPT      columns per lane in the streaming passes (1, 2, 4)
  *   BCG_OPT_FUSE_GRAM     1: Gram products fused into the epilogues of the hop
  *                         and the streaming passes (G = 4 m^2 P^H P + T^H T)
+ *   BCG_OPT_HOP_KERNEL    1: lane-split hop (the four lane groups of a wave take
+ *                         one direction each for 16 sites), 2: site-parallel hop
+ *                         (lane groups share sites, BCG_OPT_HOP_TPB); default by
+ *                         lattice size
+ *   BCG_OPT_GRAM_KERNEL   1: Gram products on the matrix cores (FP64 MFMA) for
+ *                         N > 8, 2: on the vector ALUs
+ *   BCG_OPT_SMALL_THREADS threads (64, 256, 1024) of the one-workgroup N x N
+ *                         kernels, used when N^2 <= 4 x threads
  * Returns BCG_ERR_ARG for an unknown option. */
 enum { BCG_OPT_HOP_TR = 0, BCG_OPT_HOP_TPB = 1, BCG_OPT_HOP_PIPELINE = 2, BCG_OPT_PASS_CPT = 3,
-       BCG_OPT_FUSE_GRAM = 4, BCG_OPT_COUNT = 5 };
+       BCG_OPT_FUSE_GRAM = 4, BCG_OPT_HOP_KERNEL = 5, BCG_OPT_GRAM_KERNEL = 6, BCG_OPT_SMALL_THREADS = 7,
+       BCG_OPT_COUNT = 8 };
 int bcg_set_option(bcg_ctx *ctx, int option, int value);
 
 /* Per-kernel timing with HIP events on the context's stream.  mask: bit set of

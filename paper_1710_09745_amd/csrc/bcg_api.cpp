@@ -197,14 +197,18 @@ int check_ready(bcg_ctx* ctx) {
 // ---- building blocks -----------------------------------------------------------------------
 long nvec(bcg_ctx* ctx, int N) { return (long)N * 3 * ctx->Vh; }
 
-HopShape shape(bcg_ctx* ctx, int N) {
-    return hop_shape(N, ctx->opt[BCG_OPT_HOP_TR], ctx->opt[BCG_OPT_HOP_TPB], ctx->opt[BCG_OPT_HOP_PIPELINE]);
+bool gram_mfma(bcg_ctx* ctx) { return ctx->opt[BCG_OPT_GRAM_KERNEL] != 2; }
+
+HopShape shape(bcg_ctx* ctx, Prec p, int N, bool fused) {
+    return hop_shape(p, N, ctx->opt[BCG_OPT_HOP_TR], ctx->opt[BCG_OPT_HOP_TPB], ctx->opt[BCG_OPT_HOP_PIPELINE],
+                     ctx->opt[BCG_OPT_HOP_KERNEL], ctx->g, fused);
 }
 
 int hop(bcg_ctx* ctx, Prec p, int out_parity, const void* in, void* out, const void* ctr, int N,
         int epi, const int* halt, double* dot = nullptr, double2* partials = nullptr) {
     const void* Wp = (p == Prec::FP64) ? ctx->W64[out_parity] : ctx->Wsl[out_parity];
-    HopShape h = shape(ctx, N);
+    HopShape h = shape(ctx, p, N, partials != nullptr);
+    if (epi == EPI_MASS_DOT_) h = HopShape{1, 1, h.pf, 1};  // the CG path: one column, direction split
     Prof pr(ctx, out_parity == 1 ? BCG_K_HOP_OE : BCG_K_HOP_EO);
     HIPCK(launch_hop(p, ctx->nl, Wp, in, out, ctr, 4.0 * ctx->mass * ctx->mass, N, ctx->g,
                      out_parity, epi, h, halt, dot, partials, ctx->stream));
@@ -217,7 +221,7 @@ int hop(bcg_ctx* ctx, Prec p, int out_parity, const void* in, void* out, const v
 // than the separate Gram kernels on MI355X, so they are opt-in (BCG_OPT_FUSE_GRAM).
 bool fused_ok(bcg_ctx* ctx, Prec p, int N) {
     if (!ctx->opt[BCG_OPT_FUSE_GRAM]) return false;
-    return hop_tile_bytes(p, N, shape(ctx, N)) > 0 && fused_tile_bytes(p, N) > 0;
+    return hop_tile_bytes(p, N, shape(ctx, p, N, true)) > 0 && fused_tile_bytes(p, N) > 0;
 }
 
 int reduce(bcg_ctx* ctx, const double2* pa, int na, const double2* pb, int nb, double alpha, int N,
@@ -234,17 +238,17 @@ int apply64(bcg_ctx* ctx, const void* in, void* out, void* tmp, int N, const int
     return BCG_OK;
 }
 
-// partials of A^H B into part (count gram_parts(N, Vh))
+// partials of A^H B into part (count gram_parts(N, Vh, gram_mfma(ctx)))
 int gram_partials(bcg_ctx* ctx, Prec p, const void* A, const void* B, int N, double2* part, const int* halt) {
     Prof pr(ctx, BCG_K_GRAM);
-    HIPCK(launch_gram(p, A, B, N, (int)ctx->Vh, part, halt, ctx->stream));
+    HIPCK(launch_gram(p, A, B, N, (int)ctx->Vh, part, halt, gram_mfma(ctx), ctx->stream));
     return BCG_OK;
 }
 
 // out = A^H B  (N x N, FP64, leading dimension 64)
 int gram(bcg_ctx* ctx, Prec p, const void* A, const void* B, int N, double2* out, const int* halt) {
     RETCK(gram_partials(ctx, p, A, B, N, ctx->partials, halt));
-    return reduce(ctx, ctx->partials, gram_parts(N, (int)ctx->Vh), nullptr, 0, 0.0, N, out, halt);
+    return reduce(ctx, ctx->partials, gram_parts(N, (int)ctx->Vh, gram_mfma(ctx)), nullptr, 0, 0.0, N, out, halt);
 }
 
 int colnorms(bcg_ctx* ctx, const double2* V, int N, double* out) {
@@ -343,7 +347,7 @@ int bcg_create(bcg_ctx** out, const int dims[4], int improved, void* hip_stream)
               hipHostMalloc(&ctx->h_cg, sizeof(CgState)) == hipSuccess &&
               hipMalloc(&ctx->mats, sizeof(double2) * M_COUNT * MAXN * MAXN) == hipSuccess &&
               hipMalloc(&ctx->partials, sizeof(double2) * 3 * GRAM_BLOCKS * MAXN * MAXN) == hipSuccess &&
-              hipMalloc(&ctx->nparts, sizeof(double) * ((long)NORM_BLOCKS * MAXN + ctx->Vh / 256 + 1)) == hipSuccess &&
+              hipMalloc(&ctx->nparts, sizeof(double) * ((long)NORM_BLOCKS * MAXN + hop_dot_blocks(ctx->g) + 1)) == hipSuccess &&
               hipMalloc(&ctx->d_vec, sizeof(double) * 4 * MAXN) == hipSuccess &&
               hipMalloc(&ctx->d_flags, sizeof(int) * 16) == hipSuccess &&
               hipHostMalloc(&ctx->h_vec, sizeof(double) * 4 * MAXN) == hipSuccess;
@@ -554,7 +558,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
     RETCK(gram(ctx, Prec::FP64, R64, R64, N, M(ctx, M_H), nullptr));
     {
         Prof pr(ctx, BCG_K_SMALL);
-        HIPCK(launch_small_init(M(ctx, M_H), M(ctx, M_C), M(ctx, M_CINV), st, N, s));
+        HIPCK(launch_small_init(M(ctx, M_H), M(ctx, M_C), M(ctx, M_CINV), st, N, ctx->opt[BCG_OPT_SMALL_THREADS], s));
     }
     int cur = 0;
     {
@@ -566,8 +570,8 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
     // kernel that last wrote P (here the initial P = Q)
     const bool fuse = fused_ok(ctx, ps, N);
     const double m2 = 4.0 * ctx->mass * ctx->mass;
-    int n_pp = gram_parts(N, Vh);
-    const int n_tt = hop_grid(ctx->g, shape(ctx, N), true);
+    int n_pp = gram_parts(N, Vh, gram_mfma(ctx));
+    const int n_tt = hop_grid(ctx->g, shape(ctx, ps, N, true), true);
     const int n_h = fused_grid(Vh);
     if (fuse) RETCK(gram_partials(ctx, ps, Pb[cur], Pb[cur], N, ctx->part_pp, halt));
     RETCK(read_state(ctx));
@@ -614,7 +618,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
             }
             {
                 Prof pr(ctx, BCG_K_SMALL);
-                HIPCK(launch_small1(M(ctx, M_G), M(ctx, M_C), M(ctx, M_BETA), M(ctx, M_BETAC), st, N, s));
+                HIPCK(launch_small1(M(ctx, M_G), M(ctx, M_C), M(ctx, M_BETA), M(ctx, M_BETAC), st, N, ctx->opt[BCG_OPT_SMALL_THREADS], s));
             }
             if (fuse) {
                 {
@@ -631,7 +635,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
             }
             {
                 Prof pr(ctx, BCG_K_SMALL);
-                HIPCK(launch_small2(M(ctx, M_H), M(ctx, M_C), M(ctx, M_SINV), M(ctx, M_SH), st, N, s));
+                HIPCK(launch_small2(M(ctx, M_H), M(ctx, M_C), M(ctx, M_SINV), M(ctx, M_SH), st, N, ctx->opt[BCG_OPT_SMALL_THREADS], s));
             }
             {
                 Prof pr(ctx, BCG_K_PASS_B);
@@ -680,7 +684,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
         {
             Prof pr(ctx, BCG_K_SMALL);
             HIPCK(launch_small_ru(M(ctx, M_HR), M(ctx, M_C), M(ctx, M_CINV), M(ctx, M_SH), st, d_true,
-                                  ru_skip, reason == HALT_CONVERGED ? 1 : 0, N, s));
+                                  ru_skip, reason == HALT_CONVERGED ? 1 : 0, N, ctx->opt[BCG_OPT_SMALL_THREADS], s));
         }
         {
             Prof pr(ctx, BCG_K_OTHER);
@@ -689,7 +693,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
         }
         if (fuse) {
             RETCK(gram_partials(ctx, ps, Pb[1 - cur], Pb[1 - cur], N, ctx->part_pp, ru_skip));
-            n_pp = gram_parts(N, Vh);
+            n_pp = gram_parts(N, Vh, gram_mfma(ctx));
         }
         RETCK(read_state(ctx));
         if (hs.reason == HALT_DONE) {

@@ -114,10 +114,195 @@ k_gram(const typename S::pair* __restrict__ A, const float* __restrict__ As_,
     gram_finish<NB>(acc, As, partials + (long)blockIdx.x * NB * NB);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Gram on the matrix cores (NB = 16, 32, 64).  Each wave takes chunks of ROWS
+// consecutive rows (sites of one colour), stages them in LDS (loaded site-
+// coalesced, exact in the tile's element type), and feeds 16 x 4 slices to
+// v_mfma_f64_16x16x4f64: with X = Xr + i Xi and 16-column tiles a, b,
+//   Re G_ab = Xr_a^T Yr_b + Xi_a^T Yi_b,   Im G_ab = Xr_a^T Yi_b - Xi_a^T Yr_b.
+// Only tiles a <= b are formed (the Gram is Hermitian; the lower tiles are
+// written as the conjugate transpose).  For A == B the diagonal tile needs three
+// products: Re G_aa as above and Im G_aa = M - M^T with M = Xr_a^T Xi_a.
+// Operand layout of the 16x16x4 instruction: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; accumulator element r of lane l is D[4 r + l / 16][l % 16].
+// The four waves' accumulators are summed in a fixed order in LDS at the end.
+// ---------------------------------------------------------------------------------------------
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+template <typename S, int NB, bool SAME> struct MfmaGram {
+    using E = typename TileElem<S>::type;
+    static constexpr int NT = NB / 16;
+    static constexpr int NUP = NT * (NT + 1) / 2;
+    // rows per wave chunk: 16, or 8 or 4 when the per-wave tiles would exceed 64 KB per workgroup
+    static constexpr int TB = 4 * (NB + 1) * (int)sizeof(C2<E>) * (SAME ? 1 : 2);  // bytes per row
+    static constexpr int ROWS = (16 * TB <= 65536) ? 16 : ((8 * TB <= 65536) ? 8 : 4);
+    static constexpr int LD = NB + 1;
+    static constexpr size_t tile_bytes = (size_t)4 * ROWS * LD * sizeof(C2<E>) * (SAME ? 1 : 2);
+};
+
+template <typename S, int NB, bool SAME>
+__global__ void __launch_bounds__(256)
+k_gram_mfma(const typename S::pair* __restrict__ A, const float* __restrict__ As_,
+            const typename S::pair* __restrict__ B, const float* __restrict__ Bs_, int N, int Vh,
+            double2* __restrict__ partials, const int* __restrict__ halt) {
+    using G = MfmaGram<S, NB, SAME>;
+    using E = typename G::E;
+    constexpr int NT = G::NT, ROWS = G::ROWS, LD = G::LD, QG = 64 / ROWS;
+    extern __shared__ unsigned char lds_raw[];
+    C2<E>* ta = reinterpret_cast<C2<E>*>(lds_raw);
+    C2<E>* tb = SAME ? ta : ta + 4 * ROWS * LD;
+    if (halt != nullptr && *halt) return;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    C2<E>* wa = ta + w * ROWS * LD;
+    C2<E>* wb = tb + w * ROWS * LD;
+    // accumulators per upper tile: Re G and Im G; for A == B the diagonal tiles keep
+    // M = Xr^T Xi in the second one (Im G = M - M^T at the end)
+    dvec4 acc_re[G::NUP], acc_im[G::NUP];
+#pragma unroll
+    for (int t = 0; t < G::NUP; ++t) {
+        acc_re[t] = dvec4{0.0, 0.0, 0.0, 0.0};
+        acc_im[t] = dvec4{0.0, 0.0, 0.0, 0.0};
+    }
+    const int nchunks = ((Vh + ROWS - 1) / ROWS) * 3;
+    const int ls = lane % ROWS, lq = lane / ROWS;
+    // the next chunk is loaded into registers while the current one is multiplied
+    C2<E> ra[NB / QG], rb[SAME ? 1 : NB / QG];
+    auto fetch = [&](int ch) {
+        const int c = ch % 3, site = (ch / 3) * ROWS + ls;
+        const bool ok = site < Vh;
+#pragma unroll
+        for (int jj = 0; jj < NB / QG; ++jj) {
+            const int j = jj * QG + lq;
+            C2<double> v{0.0, 0.0};
+            if (ok && j < N) v = load_one_d<S, 3>(A, As_, Vh, j, c, site);
+            ra[jj] = C2<E>{(E)v.re, (E)v.im};
+            if constexpr (!SAME) {
+                C2<double> u{0.0, 0.0};
+                if (ok && j < N) u = load_one_d<S, 3>(B, Bs_, Vh, j, c, site);
+                rb[jj] = C2<E>{(E)u.re, (E)u.im};
+            }
+        }
+    };
+    const int stride = gridDim.x * 4;
+    int ch = blockIdx.x * 4 + w;
+    if (ch < nchunks) fetch(ch);
+    for (; ch < nchunks; ch += stride) {
+        // stage ROWS x NB: lane (ls, lq) holds columns lq, lq + QG, ...
+#pragma unroll
+        for (int jj = 0; jj < NB / QG; ++jj) {
+            wa[ls * LD + jj * QG + lq] = ra[jj];
+            if constexpr (!SAME) wb[ls * LD + jj * QG + lq] = rb[jj];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (ch + stride < nchunks) fetch(ch + stride);
+#pragma unroll
+        for (int kk = 0; kk < ROWS / 4; ++kk) {
+            const int row = 4 * kk + (lane >> 4), col = lane & 15;
+            double ar[NT], ai[NT], br[NT], bi[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const C2<E> a = wa[row * LD + 16 * t + col];
+                ar[t] = (double)a.re;
+                ai[t] = (double)a.im;
+                if (!SAME) {
+                    const C2<E> b = wb[row * LD + 16 * t + col];
+                    br[t] = (double)b.re;
+                    bi[t] = (double)b.im;
+                } else {
+                    br[t] = ar[t];
+                    bi[t] = ai[t];
+                }
+            }
+            int u = 0;
+#pragma unroll
+            for (int ta_ = 0; ta_ < NT; ++ta_)
+#pragma unroll
+                for (int tb_ = ta_; tb_ < NT; ++tb_, ++u) {
+                    acc_re[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[ta_], br[tb_], acc_re[u], 0, 0, 0);
+                    acc_re[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[ta_], bi[tb_], acc_re[u], 0, 0, 0);
+                    acc_im[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[ta_], bi[tb_], acc_im[u], 0, 0, 0);
+                    if (!(SAME && ta_ == tb_))
+                        acc_im[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[ta_], br[tb_], acc_im[u], 0, 0, 0);
+                }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // fixed-order sum of the four waves, one upper tile at a time
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(lds_raw);  // [4 waves][2][256]
+    double2* out = partials + (long)blockIdx.x * NB * NB;
+    int u = 0;
+#pragma unroll
+    for (int ta_ = 0; ta_ < NT; ++ta_)
+#pragma unroll
+        for (int tb_ = ta_; tb_ < NT; ++tb_, ++u) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int e = (4 * r + (lane >> 4)) * 16 + (lane & 15);
+                red[(w * 2 + 0) * 256 + e] = acc_re[u][r];
+                red[(w * 2 + 1) * 256 + e] = acc_im[u][r];
+            }
+            __syncthreads();
+            {
+                const int e = threadIdx.x, i = e >> 4, j = e & 15;
+                const int et = j * 16 + i;  // transposed entry
+                double re = 0.0, im = 0.0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    re += red[(v * 2 + 0) * 256 + e];
+                    if (SAME && ta_ == tb_) im += red[(v * 2 + 1) * 256 + e] - red[(v * 2 + 1) * 256 + et];
+                    else im += red[(v * 2 + 1) * 256 + e];
+                }
+                const int gi = 16 * ta_ + i, gj = 16 * tb_ + j;
+                out[gi * NB + gj] = make_double2(re, im);
+                if (ta_ != tb_) out[gj * NB + gi] = make_double2(re, -im);
+            }
+            __syncthreads();
+        }
+}
+
+template <typename S, int NB>
+static void gram_mfma_go(const void* A, const void* B, int N, int Vh, double2* partials, const int* halt,
+                         hipStream_t s, int grid) {
+    using P = typename S::pair;
+    const float* as = scale_of<S>(A, N, 3, Vh);
+    const float* bs = scale_of<S>(B, N, 3, Vh);
+    if (A == B) {
+        using G = MfmaGram<S, NB, true>;
+        const size_t lds = G::tile_bytes > 4 * 2 * 256 * 8 ? G::tile_bytes : 4 * 2 * 256 * 8;
+        hipLaunchKernelGGL((k_gram_mfma<S, NB, true>), dim3(grid), dim3(256), lds, s, (const P*)A, as, (const P*)B,
+                           bs, N, Vh, partials, halt);
+    } else {
+        using G = MfmaGram<S, NB, false>;
+        const size_t lds = G::tile_bytes > 4 * 2 * 256 * 8 ? G::tile_bytes : 4 * 2 * 256 * 8;
+        hipLaunchKernelGGL((k_gram_mfma<S, NB, false>), dim3(grid), dim3(256), lds, s, (const P*)A, as,
+                           (const P*)B, bs, N, Vh, partials, halt);
+    }
+}
+
+// workgroups of the matrix-core Gram: one wave per 16-row chunk at most (the
+// kernel strides over chunks, so the grid does not depend on its chunk size)
+static int gram_mfma_grid(int Vh) {
+    const int waves = (((Vh + 15) / 16) * 3 + 3) / 4;
+    return waves < GRAM_BLOCKS ? waves : GRAM_BLOCKS;
+}
+
 template <typename S>
 static void gram_t(const void* A, const void* B, int N, int Vh, double2* partials, const int* halt,
-                   hipStream_t s, int nb) {
+                   hipStream_t s, int nb, bool mfma) {
     using P = typename S::pair;
+    if (mfma && nb >= 16) {
+        const int grid = gram_mfma_grid(Vh);
+        if (nb == 16) gram_mfma_go<S, 16>(A, B, N, Vh, partials, halt, s, grid);
+        else if (nb == 32) gram_mfma_go<S, 32>(A, B, N, Vh, partials, halt, s, grid);
+        else gram_mfma_go<S, 64>(A, B, N, Vh, partials, halt, s, grid);
+        return;
+    }
     float* as = scale_of<S>(A, N, 3, Vh);
     float* bs = scale_of<S>(B, N, 3, Vh);
     auto go = [&](auto kern, int sites) {
@@ -146,25 +331,26 @@ static int gram_sites(int nb) {
     }
 }
 
-static int gram_nparts(int Vh, int nb) {
+static int gram_nparts(int Vh, int nb, bool mfma) {
+    if (mfma && nb >= 16) return gram_mfma_grid(Vh);
     const int S = gram_sites(nb);
     const int ntiles = (Vh + S - 1) / S;
     return ntiles < GRAM_BLOCKS ? ntiles : GRAM_BLOCKS;
 }
 
 hipError_t launch_gram(Prec prec, const void* A, const void* B, int N, int Vh, double2* partials,
-                       const int* halt, hipStream_t s) {
+                       const int* halt, bool mfma, hipStream_t s) {
     const int nb = pad_n(N);
     switch (prec) {
-        case Prec::FP64: gram_t<F64>(A, B, N, Vh, partials, halt, s, nb); break;
-        case Prec::FP32: gram_t<F32>(A, B, N, Vh, partials, halt, s, nb); break;
-        case Prec::FP16: gram_t<H16>(A, B, N, Vh, partials, halt, s, nb); break;
-        case Prec::BF16: gram_t<B16>(A, B, N, Vh, partials, halt, s, nb); break;
+        case Prec::FP64: gram_t<F64>(A, B, N, Vh, partials, halt, s, nb, mfma); break;
+        case Prec::FP32: gram_t<F32>(A, B, N, Vh, partials, halt, s, nb, mfma); break;
+        case Prec::FP16: gram_t<H16>(A, B, N, Vh, partials, halt, s, nb, mfma); break;
+        case Prec::BF16: gram_t<B16>(A, B, N, Vh, partials, halt, s, nb, mfma); break;
     }
     return hipGetLastError();
 }
 
-int gram_parts(int N, int Vh) { return gram_nparts(Vh, pad_n(N)); }
+int gram_parts(int N, int Vh, bool mfma) { return gram_nparts(Vh, pad_n(N), mfma); }
 
 // out[i*64 + j] = sum_b pa[b][e] + alpha * sum_b pb[b][e], e = i*NB + j, in a fixed
 // order: 8 entries per workgroup, 32 lanes per entry each summing every 32nd
@@ -261,7 +447,7 @@ __device__ __forceinline__ void tile_put(C2<E>* tile, int NBp1, int lane, int j,
 // Pass A:  Q <- Q - AP beta   (Alg. 1: Q S = Q - A P beta, before its QR);
 // with GR also the partials of H = Qt^H Qt (Alg. 2 on Qt).
 // ---------------------------------------------------------------------------------------------
-template <typename S, int CPT, int NB, bool GR>
+template <typename S, int CPT, int NB, bool GR, int LB = std::is_same<S, F64>::value ? 2 : 4>
 __global__ void __launch_bounds__(256)
 k_pass_a(typename S::pair* __restrict__ Q, float* __restrict__ Qs, const typename S::pair* __restrict__ AP,
          const float* __restrict__ APs, const double2* __restrict__ beta, int N, int Vh,
@@ -271,7 +457,8 @@ k_pass_a(typename S::pair* __restrict__ Q, float* __restrict__ Qs, const typenam
     extern __shared__ unsigned char lds_raw[];
     C2<E>* tile = reinterpret_cast<C2<E>*>(lds_raw);
     if (halt != nullptr && *halt) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar coefficient loads
     const int nsb = (Vh + 63) / 64;
     GramAcc<NB> acc;
     if constexpr (GR) {
@@ -280,8 +467,9 @@ k_pass_a(typename S::pair* __restrict__ Q, float* __restrict__ Qs, const typenam
             tile[e] = C2<E>{(E)0, (E)0};
     }
     for (int sb = blockIdx.x; sb < nsb; sb += gridDim.x) {
-        const int i = sb * 64 + lane;
-        const bool valid = i < Vh;
+        const int i0 = sb * 64 + lane;
+        const bool valid = i0 < Vh;
+        const int i = valid ? i0 : Vh - 1;  // spare lanes compute on the last site, store nothing
         if constexpr (GR) __syncthreads();
         for (int j0 = wave * CPT; j0 < N; j0 += 4 * CPT) {
             C2<R> acc2[CPT][3];
@@ -289,18 +477,22 @@ k_pass_a(typename S::pair* __restrict__ Q, float* __restrict__ Qs, const typenam
             for (int m = 0; m < CPT; ++m)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc2[m][c] = C2<R>{0, 0};
-            if (valid) {
-#pragma unroll 4
-                for (int l = 0; l < N; ++l) {
-                    C2<R> a[3];
-                    load_group<S, 3>(AP, APs, Vh, l, i, a);
+            // LB columns of AP per trip, loaded together (a ragged trip repeats column N - 1)
+            for (int l0 = 0; l0 < N; l0 += LB) {
+                C2<R> a[LB][3];
 #pragma unroll
-                    for (int m = 0; m < CPT; ++m) {
-                        if (j0 + m < N) {
-                            const double2 bd = beta[l * MAXN + j0 + m];
-                            const C2<R> b{(R)bd.x, (R)bd.y};
+                for (int u = 0; u < LB; ++u) load_group<S, 3>(AP, APs, Vh, l0 + u < N ? l0 + u : N - 1, i, a[u]);
 #pragma unroll
-                            for (int c = 0; c < 3; ++c) cmac(acc2[m][c], a[c], b);
+                for (int u = 0; u < LB; ++u) {
+                    if (l0 + u < N) {
+#pragma unroll
+                        for (int m = 0; m < CPT; ++m) {
+                            if (j0 + m < N) {
+                                const double2 bd = beta[(l0 + u) * MAXN + j0 + m];
+                                const C2<R> b{(R)bd.x, (R)bd.y};
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) cmac(acc2[m][c], a[u][c], b);
+                            }
                         }
                     }
                 }
@@ -308,16 +500,14 @@ k_pass_a(typename S::pair* __restrict__ Q, float* __restrict__ Qs, const typenam
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
                 if (j0 + m < N) {
-                    C2<R> q[3] = {C2<R>{0, 0}, C2<R>{0, 0}, C2<R>{0, 0}};
-                    if (valid) {
-                        load_group<S, 3>(Q, Qs, Vh, j0 + m, i, q);
+                    C2<R> q[3];
+                    load_group<S, 3>(Q, Qs, Vh, j0 + m, i, q);
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            q[c].re -= acc2[m][c].re;
-                            q[c].im -= acc2[m][c].im;
-                        }
-                        store_group_rt<S, 3, R>(Q, Qs, Vh, j0 + m, i, q);
+                    for (int c = 0; c < 3; ++c) {
+                        q[c].re -= acc2[m][c].re;
+                        q[c].im -= acc2[m][c].im;
                     }
+                    if (valid) store_group_rt<S, 3, R>(Q, Qs, Vh, j0 + m, i, q);
                     if constexpr (GR) tile_put<E, R>(tile, NB + 1, lane, j0 + m, q, valid);
                 }
             }
@@ -392,7 +582,7 @@ hipError_t launch_pass_a(Prec prec, void* Q, const void* AP, const double2* beta
 // With GR also the partials of Pn^H Pn (the P^H P term of the next iteration's
 // G = 4 m^2 P^H P + T^H T).
 // ---------------------------------------------------------------------------------------------
-template <typename S, int CPT, int NB, bool GR>
+template <typename S, int CPT, int NB, bool GR, int LB = std::is_same<S, F64>::value ? 2 : 4>
 __global__ void __launch_bounds__(256)
 k_pass_b(double2* __restrict__ X, const typename S::pair* __restrict__ Qt, const float* __restrict__ Qts,
          const typename S::pair* __restrict__ P, const float* __restrict__ Ps,
@@ -408,7 +598,8 @@ k_pass_b(double2* __restrict__ X, const typename S::pair* __restrict__ Qt, const
     if (mode == PB_SKIP) return;
     const bool full = (mode == PB_FULL);
     const bool gram = GR && full;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar coefficient loads
     const int nsb = (Vh + 63) / 64;
     GramAcc<NB> acc;
     if constexpr (GR) {
@@ -417,8 +608,9 @@ k_pass_b(double2* __restrict__ X, const typename S::pair* __restrict__ Qt, const
             tile[e] = C2<E>{(E)0, (E)0};
     }
     for (int sb = blockIdx.x; sb < nsb; sb += gridDim.x) {
-        const int i = sb * 64 + lane;
-        const bool valid = i < Vh;
+        const int i0 = sb * 64 + lane;
+        const bool valid = i0 < Vh;
+        const int i = valid ? i0 : Vh - 1;  // spare lanes compute on the last site, store nothing
         if (gram) __syncthreads();
         for (int j0 = wave * CPT; j0 < N; j0 += 4 * CPT) {
             C2<double> xa[CPT][3];
@@ -431,42 +623,48 @@ k_pass_b(double2* __restrict__ X, const typename S::pair* __restrict__ Qt, const
                     qa[m][c] = C2<R>{0, 0};
                     pa[m][c] = C2<R>{0, 0};
                 }
-            if (valid) {
-#pragma unroll 4
-                for (int l = 0; l < N; ++l) {
-                    C2<R> p[3];
-                    load_group<S, 3>(P, Ps, Vh, l, i, p);
+            // LB columns of P (and of Qt while S^{-1} has entries for this tile) per
+            // trip, loaded together; a ragged trip repeats column N - 1
+            for (int l0 = 0; l0 < N; l0 += LB) {
+                const bool needq = full && l0 < j0 + CPT;
+                C2<R> p[LB][3], q[LB][3];
+#pragma unroll
+                for (int u = 0; u < LB; ++u) load_group<S, 3>(P, Ps, Vh, l0 + u < N ? l0 + u : N - 1, i, p[u]);
+                if (needq) {
+#pragma unroll
+                    for (int u = 0; u < LB; ++u) load_group<S, 3>(Qt, Qts, Vh, l0 + u < N ? l0 + u : N - 1, i, q[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < LB; ++u) {
+                    const int l = l0 + u;
+                    if (l >= N) break;
 #pragma unroll
                     for (int m = 0; m < CPT; ++m) {
                         if (j0 + m < N) {
                             const double2 bc = betaC[l * MAXN + j0 + m];
 #pragma unroll
                             for (int c = 0; c < 3; ++c)
-                                cmac(xa[m][c], C2<double>{(double)p[c].re, (double)p[c].im}, C2<double>{bc.x, bc.y});
+                                cmac(xa[m][c], C2<double>{(double)p[u][c].re, (double)p[u][c].im}, C2<double>{bc.x, bc.y});
                         }
                     }
                     if (full) {
-                        if (l >= j0) {
 #pragma unroll
-                            for (int m = 0; m < CPT; ++m) {
-                                if (j0 + m < N && l >= j0 + m) {
-                                    const double2 sh = SH[l * MAXN + j0 + m];
-                                    const C2<R> b{(R)sh.x, (R)sh.y};
+                        for (int m = 0; m < CPT; ++m) {
+                            if (j0 + m < N && l >= j0 + m) {
+                                const double2 sh = SH[l * MAXN + j0 + m];
+                                const C2<R> b{(R)sh.x, (R)sh.y};
 #pragma unroll
-                                    for (int c = 0; c < 3; ++c) cmac(pa[m][c], p[c], b);
-                                }
+                                for (int c = 0; c < 3; ++c) cmac(pa[m][c], p[u][c], b);
                             }
                         }
-                        if (l < j0 + CPT) {
-                            C2<R> q[3];
-                            load_group<S, 3>(Qt, Qts, Vh, l, i, q);
+                        if (needq) {
 #pragma unroll
                             for (int m = 0; m < CPT; ++m) {
                                 if (j0 + m < N && l <= j0 + m) {
                                     const double2 si = Sinv[l * MAXN + j0 + m];
                                     const C2<R> b{(R)si.x, (R)si.y};
 #pragma unroll
-                                    for (int c = 0; c < 3; ++c) cmac(qa[m][c], q[c], b);
+                                    for (int c = 0; c < 3; ++c) cmac(qa[m][c], q[u][c], b);
                                 }
                             }
                         }
@@ -477,13 +675,14 @@ k_pass_b(double2* __restrict__ X, const typename S::pair* __restrict__ Qt, const
             for (int m = 0; m < CPT; ++m) {
                 if (j0 + m < N) {
                     if (valid) {
+                        double2 xv[3];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) xv[c] = X[((long)(j0 + m) * 3 + c) * Vh + i];
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            const long o = ((long)(j0 + m) * 3 + c) * Vh + i;
-                            double2 xv = X[o];
-                            xv.x += xa[m][c].re;
-                            xv.y += xa[m][c].im;
-                            X[o] = xv;
+                            xv[c].x += xa[m][c].re;
+                            xv[c].y += xa[m][c].im;
+                            X[((long)(j0 + m) * 3 + c) * Vh + i] = xv[c];
                         }
                     }
                     if (full) {
@@ -573,7 +772,8 @@ k_bmul(const typename SX::pair* __restrict__ X, const float* __restrict__ Xs,
        typename SY::pair* __restrict__ Y, float* __restrict__ Ys, const double2* __restrict__ M, int N,
        int Vh, const int* __restrict__ skip) {
     if (skip != nullptr && *skip) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar coefficient loads
     const int i = blockIdx.x * 64 + lane;
     if (i >= Vh) return;
     for (int j0 = wave * CPT; j0 < N; j0 += 4 * CPT) {

@@ -14,9 +14,10 @@ constexpr int GRAM_BLOCKS = 512;  // workgroups of a Gram reduction (= rows of i
 constexpr int NORM_BLOCKS = 512;  // workgroups of a column-norm reduction
 
 struct HopShape {
-    int tr;   // right-hand sides per lane (register tile)
-    int tpb;  // lane groups per workgroup sharing the same sites (cache tile)
-    int pf;   // 1: software-pipelined link loop
+    int tr;     // right-hand sides per lane (register tile)
+    int tpb;    // site-parallel kernel: lane groups per workgroup sharing the same sites
+    int pf;     // 1: two folded matrices in flight per loop trip
+    int split;  // 1: direction-split kernel (four waves share 64 sites), 0: site-parallel
 };
 
 // bytes per stored complex number, and bytes of a [cols][K][Vh] allocation
@@ -47,7 +48,12 @@ hipError_t pack_links(const void* fat, const void* lng, void* W, const Geom& g, 
                       hipStream_t s);
 // lower-precision folded links from the FP64 ones
 hipError_t links_from64(Prec pd, const void* W64, void* Wd, int nl, long Vh, hipStream_t s);
-HopShape hop_shape(int N, int tr = 0, int tpb = 0, int pf = 0);
+// launch shape of the hop for N right-hand sides in precision p on lattice g;
+// nonzero tr, tpb override the defaults, pf: 1 on, 2 off; kernel: 1 lane split,
+// 2 site-parallel, 0 chosen by lattice size; fused (Gram epilogue) always takes
+// the site-parallel kernel
+HopShape hop_shape(Prec p, int N, int tr, int tpb, int pf, int kernel, const Geom& g, bool fused);
+// partial dot products written by the EPI_MASS_DOT hop (one right-hand side)
 int hop_dot_blocks(const Geom& g);
 // partials != nullptr (EPI_PLAIN only): also T^H T partials of the output, one per
 // workgroup of the persistent grid hop_grid(g, h, true)
@@ -60,11 +66,12 @@ enum { EPI_PLAIN_ = 0, EPI_MASS_ = 1, EPI_MASS_DOT_ = 2 };
 
 // blas.hip --------------------------------------------------------------------------------------
 // partials[b][i*NB + j] = sum over the rows of workgroup b of conj(A[row,i]) B[row,j]
+// mfma: matrix-core kernel for N > 8 (vector-ALU kernel otherwise)
 hipError_t launch_gram(Prec prec, const void* A, const void* B, int N, int Vh, double2* partials,
-                       const int* halt, hipStream_t s);
+                       const int* halt, bool mfma, hipStream_t s);
 // out[i*64 + j] = sum_b partials[b][i*NB + j]  (fixed order)
 // number of partials launch_gram writes
-int gram_parts(int N, int Vh);
+int gram_parts(int N, int Vh, bool mfma);
 // out[i*64 + j] = sum_b pa[b][i*NB + j] + alpha * sum_b pb[b][i*NB + j]  (fixed order; pb may be NULL)
 hipError_t launch_gram_reduce(const double2* pa, int na, const double2* pb, int nb, double alpha, int N,
                               double2* out, const int* halt, hipStream_t s);
@@ -122,18 +129,18 @@ hipError_t launch_cg_init(const double* partials, int Vh, CgState* st, double to
 hipError_t small_setup();
 // initial thin QR of R from H = R^H R:  C (upper) and Cinv; relres, rho_ru; halts on breakdown
 hipError_t launch_small_init(const double2* H, double2* C, double2* Cinv, SolveState* st, int N,
-                             hipStream_t s);
+                             int req, hipStream_t s);
 // beta = G^{-1}, betaC = beta C
 hipError_t launch_small1(const double2* G, const double2* C, double2* beta, double2* betaC,
-                         SolveState* st, int N, hipStream_t s);
+                         SolveState* st, int N, int req, hipStream_t s);
 // residual test, S from H = S^H S, Sinv, S^H, C <- S C; sets pb_mode / halt
 hipError_t launch_small2(const double2* H, double2* C, double2* Sinv, double2* SH, SolveState* st,
-                         int N, hipStream_t s);
+                         int N, int req, hipStream_t s);
 // reliable update from H = R^H R of the true residual: true residuals; if conv_check and
 // all <= tol: done; else C^ , C^-1, S^H = (C^ C^-1)^H, C <- C^, resume
 hipError_t launch_small_ru(const double2* H, double2* C, double2* Chinv, double2* SH,
                            SolveState* st, double* true_relres, int* ru_skip, int conv_check,
-                           int N, hipStream_t s);
+                           int N, int req, hipStream_t s);
 hipError_t launch_state_init(SolveState* st, double tol, double ru_delta, const double* bnorm,
                              int N, hipStream_t s);
 hipError_t launch_identity(double2* M, int N, hipStream_t s);

@@ -491,7 +491,12 @@ hipError_t small_setup() {
     return hipSuccess;
 }
 
-static int small_threads(int N) { return N <= 16 ? 256 : 1024; }
+// threads of the single-workgroup N x N kernels: a request of 64, 256 or 1024 is
+// honoured when every thread keeps at most four entries of an N x N matrix
+static int small_threads(int N, int req) {
+    if ((req == 64 || req == 256 || req == 1024) && N * N <= 4 * req) return req;
+    return N <= 16 ? 256 : 1024;
+}
 
 hipError_t launch_state_init(SolveState* st, double tol, double ru_delta, const double* bnorm, int N,
                              hipStream_t s) {
@@ -503,24 +508,24 @@ hipError_t launch_identity(double2* M, int N, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t launch_small_init(const double2* H, double2* C, double2* Cinv, SolveState* st, int N,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_small_init, dim3(1), dim3(small_threads(N)), small_lds(N), s, H, C, Cinv, st, N);
+                             int req, hipStream_t s) {
+    hipLaunchKernelGGL(k_small_init, dim3(1), dim3(small_threads(N, req)), small_lds(N), s, H, C, Cinv, st, N);
     return hipGetLastError();
 }
 hipError_t launch_small1(const double2* G, const double2* C, double2* beta, double2* betaC,
-                         SolveState* st, int N, hipStream_t s) {
-    hipLaunchKernelGGL(k_small1, dim3(1), dim3(small_threads(N)), small_lds(N), s, G, C, beta, betaC, st, N);
+                         SolveState* st, int N, int req, hipStream_t s) {
+    hipLaunchKernelGGL(k_small1, dim3(1), dim3(small_threads(N, req)), small_lds(N), s, G, C, beta, betaC, st, N);
     return hipGetLastError();
 }
 hipError_t launch_small2(const double2* H, double2* C, double2* Sinv, double2* SH, SolveState* st,
-                         int N, hipStream_t s) {
-    hipLaunchKernelGGL(k_small2, dim3(1), dim3(small_threads(N)), small_lds(N), s, H, C, Sinv, SH, st, N);
+                         int N, int req, hipStream_t s) {
+    hipLaunchKernelGGL(k_small2, dim3(1), dim3(small_threads(N, req)), small_lds(N), s, H, C, Sinv, SH, st, N);
     return hipGetLastError();
 }
 hipError_t launch_small_ru(const double2* H, double2* C, double2* Chinv, double2* SH,
                            SolveState* st, double* true_relres, int* ru_skip, int conv_check,
-                           int N, hipStream_t s) {
-    hipLaunchKernelGGL(k_small_ru, dim3(1), dim3(small_threads(N)), small_lds(N), s, H, C, Chinv, SH,
+                           int N, int req, hipStream_t s) {
+    hipLaunchKernelGGL(k_small_ru, dim3(1), dim3(small_threads(N, req)), small_lds(N), s, H, C, Chinv, SH,
                        st, true_relres, ru_skip, conv_check, N);
     return hipGetLastError();
 }

@@ -55,20 +55,44 @@ struct B16 {
     }
 };
 
-// A block vector (or link set) view: data pointer and, for scaled policies, the
-// scale array of its [cols][Vh] groups.
-template <typename S> struct View {
-    typename S::pair* d;
-    float* s;
-};
-template <typename S> struct CView {
-    const typename S::pair* d;
-    const float* s;
-};
+// Buffer-resource loads.  A resource is made from a wave-uniform base address
+// (SGPRs); the per-lane byte offset travels in one VGPR and the per-plane byte
+// offset in an SGPR, so a gather needs no per-load 64-bit address arithmetic.
+// Offsets from a base stay below 4 GiB: bases are re-made per column or per
+// folded matrix.  aux = 2 marks a streaming (non-temporal) load.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
+}
+enum { AUX_NONE = 0, AUX_NT = 2 };
 
-// scale array of a [cols][K][Vh] allocation
-inline size_t data_bytes(int bytes_per_pair, long cols, int K, long Vh) {
-    return (size_t)bytes_per_pair * cols * K * Vh;
+template <int AUX> __device__ __forceinline__ C2<double> buf_pair(rsrc_t r, unsigned vo, unsigned so, double) {
+    const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, AUX);
+    const double2 p = __builtin_bit_cast(double2, u);
+    return C2<double>{p.x, p.y};
+}
+template <int AUX> __device__ __forceinline__ C2<float> buf_pair(rsrc_t r, unsigned vo, unsigned so, float) {
+    const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, AUX);
+    const float2 p = __builtin_bit_cast(float2, u);
+    return C2<float>{p.x, p.y};
+}
+
+// K complex numbers of one group: component c at byte offset vo + c * plane of
+// resource d; for scaled policies the scale at byte offset svo of resource sc
+template <typename S, int K, int AUX>
+__device__ __forceinline__ void buf_group(rsrc_t d, rsrc_t sc, unsigned vo, unsigned svo, unsigned plane,
+                                          C2<typename S::real> v[K]) {
+    if constexpr (!S::scaled) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) v[c] = buf_pair<AUX>(d, vo, c * plane, (typename S::real)0);
+    } else {
+        const float s = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sc, svo, 0, AUX));
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            const unsigned int u = __builtin_amdgcn_raw_buffer_load_b32(d, vo, c * plane, AUX);
+            v[c] = C2<float>{S::dec((unsigned short)(u & 0xffffu)) * s, S::dec((unsigned short)(u >> 16)) * s};
+        }
+    }
 }
 
 // streaming (non-temporal) loads: data read once, kept out of the way of reused lines

@@ -244,19 +244,59 @@ def test_fused_gram_path_matches_oracle(prec, n):
         assert col_rel_err(X4.cpu().numpy(), Xo).max() <= 1e-10
 
 
-@pytest.mark.parametrize("tr,tpb,pf,cpt", [(1, 4, 1, 1), (2, 2, 0, 2), (8, 1, 1, 4), (4, 4, 1, 2)])
-def test_launch_shapes_match_oracle(tr, tpb, pf, cpt):
-    """Every hop register tile / lane-group / pipelining choice and pass column
-    tile gives the same operator and iterates."""
+@pytest.mark.parametrize("kernel,tr,tpb,pf,cpt", [(2, 1, 4, 1, 1), (2, 2, 2, 0, 2), (2, 8, 1, 1, 4), (2, 4, 4, 1, 2),
+                                                  (1, 1, 0, 0, 1), (1, 2, 0, 1, 2), (1, 8, 0, 1, 4), (0, 0, 0, 0, 0)])
+def test_launch_shapes_match_oracle(kernel, tr, tpb, pf, cpt):
+    """Both hop kernels (direction split, site-parallel) with every register tile,
+    lane-group and pipelining choice, and every pass column tile, give the same
+    operator and iterates."""
     dims = (6, 6, 6, 6)
     n = 9
     fat, lng, B = inputs(dims, True, n, 6900)
     m = 0.15
-    ctx = context(dims, True, fat, lng, m, tol=1e-14, ru_delta=0.0, max_iter=3)
-    for name, v in [("hop_tr", tr), ("hop_tpb", tpb), ("hop_pipeline", pf), ("pass_cpt", cpt)]:
-        ctx.set_option(name, v)
     op = oracle.Operator(dims, fat, lng, m)
-    assert col_rel_err(ctx.apply(to_dev(B)).cpu().numpy(), op.apply(B)).max() <= 1e-12
-    X3, _ = ctx.solve(to_dev(B), raise_on_error=False)
+    for prec, tol in [("fp64", 1e-12), ("fp32", 1e-5)]:
+        ctx = context(dims, True, fat, lng, m, tol=1e-14, ru_delta=0.0, max_iter=3, prec=prec)
+        for name, v in [("hop_kernel", kernel), ("hop_tr", tr), ("hop_tpb", tpb), ("hop_pipeline", pf),
+                        ("pass_cpt", cpt)]:
+            ctx.set_option(name, v)
+        assert col_rel_err(ctx.apply(to_dev(B)).cpu().numpy(), op.apply(B)).max() <= 1e-12
+        X3, _ = ctx.solve(to_dev(B), raise_on_error=False)
+        Xo, _ = oracle.block_cg_rq(op.apply, B, 1e-14, max_iter=3)
+        assert col_rel_err(X3.cpu().numpy(), Xo).max() <= (1e-10 if prec == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("n", [16, 24, 40, 64])
+def test_gram_kernels_match_oracle(n):
+    """Matrix-core (FP64 MFMA, Hermitian upper tiles) and vector-ALU Gram kernels
+    give the same iterates as the oracle, for one, two and four 16-column tiles
+    (ragged N included)."""
+    dims = (6, 6, 6, 8)
+    fat, lng, B = inputs(dims, True, n, 7000 + n)
+    m = 0.15
+    op = oracle.Operator(dims, fat, lng, m)
     Xo, _ = oracle.block_cg_rq(op.apply, B, 1e-14, max_iter=3)
+    for kernel in (1, 2):
+        ctx = context(dims, True, fat, lng, m, tol=1e-14, ru_delta=0.0, max_iter=3)
+        ctx.set_option("gram_kernel", kernel)
+        X3, _ = ctx.solve(to_dev(B), raise_on_error=False)
+        assert col_rel_err(X3.cpu().numpy(), Xo).max() <= 1e-10, f"gram_kernel={kernel}"
+    for prec in ("fp32", "bf16"):
+        ctx = context(dims, True, fat, lng, m, tol=1e-8, prec=prec)
+        X, info = ctx.solve(to_dev(B))
+        assert true_rel_res(op, B, X.cpu().numpy()).max() <= 1e-8
+
+
+@pytest.mark.parametrize("n,threads", [(4, 64), (16, 64), (16, 1024), (32, 256), (64, 1024)])
+def test_small_kernel_threads_match_oracle(n, threads):
+    """The one-workgroup N x N kernels give the same iterates with one, four or
+    sixteen waves (a request that would exceed four entries per thread falls back)."""
+    dims = (6, 6, 6, 8)
+    fat, lng, B = inputs(dims, True, n, 7100 + n)
+    m = 0.15
+    op = oracle.Operator(dims, fat, lng, m)
+    Xo, _ = oracle.block_cg_rq(op.apply, B, 1e-14, max_iter=3)
+    ctx = context(dims, True, fat, lng, m, tol=1e-14, ru_delta=0.0, max_iter=3)
+    ctx.set_option("small_threads", threads)
+    X3, _ = ctx.solve(to_dev(B), raise_on_error=False)
     assert col_rel_err(X3.cpu().numpy(), Xo).max() <= 1e-10
