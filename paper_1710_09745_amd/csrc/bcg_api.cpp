@@ -199,6 +199,9 @@ long nvec(bcg_ctx* ctx, int N) { return (long)N * 3 * ctx->Vh; }
 
 bool gram_mfma(bcg_ctx* ctx) { return ctx->opt[BCG_OPT_GRAM_KERNEL] != 2; }
 
+// 64-site blocks per time slice for the XCD order of the streaming passes
+int bps64(bcg_ctx* ctx) { return blocks_per_slice(ctx->g, 64); }
+
 HopShape shape(bcg_ctx* ctx, Prec p, int N, bool fused) {
     return hop_shape(p, N, ctx->opt[BCG_OPT_HOP_TR], ctx->opt[BCG_OPT_HOP_TPB], ctx->opt[BCG_OPT_HOP_PIPELINE],
                      ctx->opt[BCG_OPT_HOP_KERNEL], ctx->g, fused);
@@ -337,6 +340,7 @@ int bcg_create(bcg_ctx** out, const int dims[4], int improved, void* hip_stream)
     ctx->V = V;
     ctx->Vh = V / 2;
     ctx->g.Vh = (int)ctx->Vh;
+    ctx->g.slab = 1;
     ctx->improved = improved;
     ctx->nl = improved ? 16 : 8;
     ctx->stream = (hipStream_t)hip_stream;
@@ -623,13 +627,13 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
             if (fuse) {
                 {
                     Prof pr(ctx, BCG_K_PASS_A);
-                    HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, ctx->partials, ctx->opt[BCG_OPT_PASS_CPT], s));
+                    HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, ctx->partials, ctx->opt[BCG_OPT_PASS_CPT], bps64(ctx), s));
                 }
                 RETCK(reduce(ctx, ctx->partials, n_h, nullptr, 0, 0.0, N, M(ctx, M_H), halt));
             } else {
                 {
                     Prof pr(ctx, BCG_K_PASS_A);
-                    HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, nullptr, ctx->opt[BCG_OPT_PASS_CPT], s));
+                    HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, nullptr, ctx->opt[BCG_OPT_PASS_CPT], bps64(ctx), s));
                 }
                 RETCK(gram(ctx, ps, Q, Q, N, M(ctx, M_H), halt));
             }
@@ -640,7 +644,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
             {
                 Prof pr(ctx, BCG_K_PASS_B);
                 HIPCK(launch_pass_b(ps, X, Q, P, Qn, Pn, M(ctx, M_BETAC), M(ctx, M_SINV), M(ctx, M_SH),
-                                    N, Vh, st, fuse ? ctx->part_pp : nullptr, ctx->opt[BCG_OPT_PASS_CPT], s));
+                                    N, Vh, st, fuse ? ctx->part_pp : nullptr, ctx->opt[BCG_OPT_PASS_CPT], bps64(ctx), s));
             }
             n_pp = fused_grid(Vh);
             c = 1 - c;
@@ -864,6 +868,7 @@ int bcg_set_option(bcg_ctx* ctx, int option, int value) {
     if (!ctx) return BCG_ERR_ARG;
     if (option < 0 || option >= BCG_OPT_COUNT) return fail(ctx, BCG_ERR_ARG, "unknown option");
     ctx->opt[option] = value;
+    if (option == BCG_OPT_SITE_ORDER) ctx->g.slab = (value == 2) ? 0 : 1;
     return BCG_OK;
 }
 

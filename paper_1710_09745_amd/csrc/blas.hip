@@ -451,7 +451,7 @@ template <typename S, int CPT, int NB, bool GR, int LB = std::is_same<S, F64>::v
 __global__ void __launch_bounds__(256)
 k_pass_a(typename S::pair* __restrict__ Q, float* __restrict__ Qs, const typename S::pair* __restrict__ AP,
          const float* __restrict__ APs, const double2* __restrict__ beta, int N, int Vh,
-         const int* __restrict__ halt, double2* __restrict__ partials) {
+         const int* __restrict__ halt, double2* __restrict__ partials, int bps) {
     using R = typename S::real;
     using E = typename TileElem<S>::type;
     extern __shared__ unsigned char lds_raw[];
@@ -466,7 +466,9 @@ k_pass_a(typename S::pair* __restrict__ Q, float* __restrict__ Qs, const typenam
         for (int e = threadIdx.x; e < FusedTile<S, NB>::ROWS * (NB + 1); e += 256)
             tile[e] = C2<E>{(E)0, (E)0};
     }
-    for (int sb = blockIdx.x; sb < nsb; sb += gridDim.x) {
+    for (int it = blockIdx.x; it < nsb; it += gridDim.x) {
+        int sb, tg_unused;
+        xcd_task(it, nsb, 1, bps, sb, tg_unused);
         const int i0 = sb * 64 + lane;
         const bool valid = i0 < Vh;
         const int i = valid ? i0 : Vh - 1;  // spare lanes compute on the last site, store nothing
@@ -528,46 +530,46 @@ static int pass_cpt(int N, int cpt_req) {
 
 template <typename S, int CPT, int NB, bool GR>
 static void pass_a_go(void* Q, const void* AP, const double2* beta, int N, int Vh, const int* halt,
-                      double2* partials, hipStream_t s) {
+                      double2* partials, int bps, hipStream_t s) {
     using P = typename S::pair;
     const int grid = GR ? fused_grid(Vh) : (Vh + 63) / 64;
     const size_t lds = GR ? FusedTile<S, NB>::bytes : 0;
     hipLaunchKernelGGL((k_pass_a<S, CPT, NB, GR>), dim3(grid), dim3(256), lds, s, (P*)Q, scale_of<S>(Q, N, 3, Vh),
-                       (const P*)AP, scale_of<S>(AP, N, 3, Vh), beta, N, Vh, halt, partials);
+                       (const P*)AP, scale_of<S>(AP, N, 3, Vh), beta, N, Vh, halt, partials, bps);
 }
 
 template <typename S, int CPT>
 static void pass_a_nb(void* Q, const void* AP, const double2* beta, int N, int Vh, const int* halt,
-                      double2* partials, hipStream_t s) {
-    if (partials == nullptr) return pass_a_go<S, CPT, 1, false>(Q, AP, beta, N, Vh, halt, nullptr, s);
+                      double2* partials, int bps, hipStream_t s) {
+    if (partials == nullptr) return pass_a_go<S, CPT, 1, false>(Q, AP, beta, N, Vh, halt, nullptr, bps, s);
     switch (pad_n(N)) {
-        case 1: return pass_a_go<S, CPT, 1, true>(Q, AP, beta, N, Vh, halt, partials, s);
-        case 2: return pass_a_go<S, CPT, 2, true>(Q, AP, beta, N, Vh, halt, partials, s);
-        case 4: return pass_a_go<S, CPT, 4, true>(Q, AP, beta, N, Vh, halt, partials, s);
-        case 8: return pass_a_go<S, CPT, 8, true>(Q, AP, beta, N, Vh, halt, partials, s);
-        case 16: return pass_a_go<S, CPT, 16, true>(Q, AP, beta, N, Vh, halt, partials, s);
+        case 1: return pass_a_go<S, CPT, 1, true>(Q, AP, beta, N, Vh, halt, partials, bps, s);
+        case 2: return pass_a_go<S, CPT, 2, true>(Q, AP, beta, N, Vh, halt, partials, bps, s);
+        case 4: return pass_a_go<S, CPT, 4, true>(Q, AP, beta, N, Vh, halt, partials, bps, s);
+        case 8: return pass_a_go<S, CPT, 8, true>(Q, AP, beta, N, Vh, halt, partials, bps, s);
+        case 16: return pass_a_go<S, CPT, 16, true>(Q, AP, beta, N, Vh, halt, partials, bps, s);
         default:
-            if constexpr (!std::is_same<S, F64>::value) return pass_a_go<S, CPT, 32, true>(Q, AP, beta, N, Vh, halt, partials, s);
+            if constexpr (!std::is_same<S, F64>::value) return pass_a_go<S, CPT, 32, true>(Q, AP, beta, N, Vh, halt, partials, bps, s);
     }
 }
 
 template <typename S>
 static void pass_a_t(void* Q, const void* AP, const double2* beta, int N, int Vh, const int* halt,
-                     double2* partials, int cpt_req, hipStream_t s) {
+                     double2* partials, int cpt_req, int bps, hipStream_t s) {
     const int cpt = pass_cpt(N, cpt_req);
-    if (cpt == 1) pass_a_nb<S, 1>(Q, AP, beta, N, Vh, halt, partials, s);
-    else if (cpt == 2) pass_a_nb<S, 2>(Q, AP, beta, N, Vh, halt, partials, s);
-    else pass_a_nb<S, 4>(Q, AP, beta, N, Vh, halt, partials, s);
+    if (cpt == 1) pass_a_nb<S, 1>(Q, AP, beta, N, Vh, halt, partials, bps, s);
+    else if (cpt == 2) pass_a_nb<S, 2>(Q, AP, beta, N, Vh, halt, partials, bps, s);
+    else pass_a_nb<S, 4>(Q, AP, beta, N, Vh, halt, partials, bps, s);
 }
 
 hipError_t launch_pass_a(Prec prec, void* Q, const void* AP, const double2* beta, int N, int Vh,
-                         const int* halt, double2* partials, int cpt, hipStream_t s) {
+                         const int* halt, double2* partials, int cpt, int bps, hipStream_t s) {
     if (partials != nullptr && fused_tile_bytes(prec, N) == 0) return hipErrorInvalidValue;
     switch (prec) {
-        case Prec::FP64: pass_a_t<F64>(Q, AP, beta, N, Vh, halt, partials, cpt, s); break;
-        case Prec::FP32: pass_a_t<F32>(Q, AP, beta, N, Vh, halt, partials, cpt, s); break;
-        case Prec::FP16: pass_a_t<H16>(Q, AP, beta, N, Vh, halt, partials, cpt, s); break;
-        case Prec::BF16: pass_a_t<B16>(Q, AP, beta, N, Vh, halt, partials, cpt, s); break;
+        case Prec::FP64: pass_a_t<F64>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, s); break;
+        case Prec::FP32: pass_a_t<F32>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, s); break;
+        case Prec::FP16: pass_a_t<H16>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, s); break;
+        case Prec::BF16: pass_a_t<B16>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, s); break;
     }
     return hipGetLastError();
 }
@@ -589,7 +591,7 @@ k_pass_b(double2* __restrict__ X, const typename S::pair* __restrict__ Qt, const
          typename S::pair* __restrict__ Qn, float* __restrict__ Qns, typename S::pair* __restrict__ Pn,
          float* __restrict__ Pns, const double2* __restrict__ betaC, const double2* __restrict__ Sinv,
          const double2* __restrict__ SH, int N, int Vh, const SolveState* __restrict__ stt,
-         double2* __restrict__ partials) {
+         double2* __restrict__ partials, int bps) {
     using R = typename S::real;
     using E = typename TileElem<S>::type;
     extern __shared__ unsigned char lds_raw[];
@@ -607,7 +609,9 @@ k_pass_b(double2* __restrict__ X, const typename S::pair* __restrict__ Qt, const
         for (int e = threadIdx.x; e < FusedTile<S, NB>::ROWS * (NB + 1); e += 256)
             tile[e] = C2<E>{(E)0, (E)0};
     }
-    for (int sb = blockIdx.x; sb < nsb; sb += gridDim.x) {
+    for (int it = blockIdx.x; it < nsb; it += gridDim.x) {
+        int sb, tg_unused;
+        xcd_task(it, nsb, 1, bps, sb, tg_unused);
         const int i0 = sb * 64 + lane;
         const bool valid = i0 < Vh;
         const int i = valid ? i0 : Vh - 1;  // spare lanes compute on the last site, store nothing
@@ -711,21 +715,21 @@ k_pass_b(double2* __restrict__ X, const typename S::pair* __restrict__ Qt, const
 template <typename S, int CPT, int NB, bool GR>
 static void pass_b_go(double2* X, const void* Qt, const void* P, void* Qn, void* Pn, const double2* betaC,
                       const double2* Sinv, const double2* SH, int N, int Vh, const SolveState* st,
-                      double2* partials, hipStream_t s) {
+                      double2* partials, int bps, hipStream_t s) {
     using PP = typename S::pair;
     const int grid = GR ? fused_grid(Vh) : (Vh + 63) / 64;
     const size_t lds = GR ? FusedTile<S, NB>::bytes : 0;
     hipLaunchKernelGGL((k_pass_b<S, CPT, NB, GR>), dim3(grid), dim3(256), lds, s, X, (const PP*)Qt,
                        scale_of<S>(Qt, N, 3, Vh), (const PP*)P, scale_of<S>(P, N, 3, Vh), (PP*)Qn,
                        scale_of<S>(Qn, N, 3, Vh), (PP*)Pn, scale_of<S>(Pn, N, 3, Vh), betaC, Sinv, SH, N, Vh,
-                       st, partials);
+                       st, partials, bps);
 }
 
 template <typename S, int CPT>
 static void pass_b_nb(double2* X, const void* Qt, const void* P, void* Qn, void* Pn, const double2* betaC,
                       const double2* Sinv, const double2* SH, int N, int Vh, const SolveState* st,
-                      double2* partials, hipStream_t s) {
-#define PBG(NBV, GRV) pass_b_go<S, CPT, NBV, GRV>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, s)
+                      double2* partials, int bps, hipStream_t s) {
+#define PBG(NBV, GRV) pass_b_go<S, CPT, NBV, GRV>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, bps, s)
     if (partials == nullptr) return PBG(1, false);
     switch (pad_n(N)) {
         case 1: return PBG(1, true);
@@ -742,22 +746,22 @@ static void pass_b_nb(double2* X, const void* Qt, const void* P, void* Qn, void*
 template <typename S>
 static void pass_b_t(double2* X, const void* Qt, const void* P, void* Qn, void* Pn, const double2* betaC,
                      const double2* Sinv, const double2* SH, int N, int Vh, const SolveState* st,
-                     double2* partials, int cpt_req, hipStream_t s) {
+                     double2* partials, int cpt_req, int bps, hipStream_t s) {
     const int cpt = pass_cpt(N, cpt_req);
-    if (cpt == 1) pass_b_nb<S, 1>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, s);
-    else if (cpt == 2) pass_b_nb<S, 2>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, s);
-    else pass_b_nb<S, 4>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, s);
+    if (cpt == 1) pass_b_nb<S, 1>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, bps, s);
+    else if (cpt == 2) pass_b_nb<S, 2>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, bps, s);
+    else pass_b_nb<S, 4>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, bps, s);
 }
 
 hipError_t launch_pass_b(Prec prec, double2* X, const void* Qt, const void* P, void* Qn, void* Pn,
                          const double2* betaC, const double2* Sinv, const double2* SH, int N,
-                         int Vh, const SolveState* state, double2* partials, int cpt, hipStream_t s) {
+                         int Vh, const SolveState* state, double2* partials, int cpt, int bps, hipStream_t s) {
     if (partials != nullptr && fused_tile_bytes(prec, N) == 0) return hipErrorInvalidValue;
     switch (prec) {
-        case Prec::FP64: pass_b_t<F64>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, s); break;
-        case Prec::FP32: pass_b_t<F32>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, s); break;
-        case Prec::FP16: pass_b_t<H16>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, s); break;
-        case Prec::BF16: pass_b_t<B16>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, s); break;
+        case Prec::FP64: pass_b_t<F64>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, s); break;
+        case Prec::FP32: pass_b_t<F32>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, s); break;
+        case Prec::FP16: pass_b_t<H16>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, s); break;
+        case Prec::BF16: pass_b_t<B16>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, s); break;
     }
     return hipGetLastError();
 }

@@ -55,6 +55,7 @@ template <typename R> __device__ __forceinline__ void cmac_conj(C2<R>& acc, C2<R
 struct Geom {
     int L[4];
     int Vh;
+    int slab;  // 1: XCD slab order of site blocks (xcd_task), 0: identity order
 };
 
 // coordinates of the site with checkerboard index cb on parity p
@@ -83,6 +84,36 @@ __device__ __forceinline__ int neighbour_cb(const Geom& g, const int x[4], int m
     else if (mu == 2) y2 = v;
     else y3 = v;
     return (y0 + g.L[0] * (y1 + g.L[1] * (y2 + g.L[2] * y3))) >> 1;
+}
+
+// Site-block order for XCD locality.  Workgroups are handed to the eight XCDs
+// round robin (workgroup b on XCD b % 8), and each XCD has its own L2.  With bps
+// site blocks per time slice (bps % 8 == 0 and nsb a multiple of bps), XCD x takes
+// the x-th eighth of every time slice and all XCDs sweep the slices together: the
+// slices a stencil reaches (t +- 3) are then shared in the Infinity Cache, and every
+// kernel that uses this order puts a site on the same XCD, so a block vector written
+// by one kernel is re-read from that XCD's L2 by the next.  Tasks are (site block,
+// tile group) pairs with the ntg tile groups of a block consecutive on its XCD.
+// Otherwise the identity order.  A bijection of [0, nsb * ntg).
+__device__ __forceinline__ void xcd_task(int b, int nsb, int ntg, int bps, int& sb, int& tg) {
+    if (bps > 0 && (bps & 7) == 0 && nsb % bps == 0) {
+        const int x = b & 7, q = b >> 3;
+        const int per_t = (bps >> 3) * ntg;
+        const int t = q / per_t, r = q - t * per_t;
+        const int k = r / ntg;
+        tg = r - k * ntg;
+        sb = t * bps + x * (bps >> 3) + k;
+        return;
+    }
+    sb = b / ntg;
+    tg = b - sb * ntg;
+}
+
+// site blocks of spb sites per time slice, or 0 when a slice is not a whole number of blocks
+__host__ __device__ inline int blocks_per_slice(const Geom& g, int spb) {
+    if (!g.slab) return 0;
+    const int slice = g.L[0] * g.L[1] * g.L[2] / 2;
+    return (slice % spb == 0) ? slice / spb : 0;
 }
 
 // staggered phase eta_mu(x)

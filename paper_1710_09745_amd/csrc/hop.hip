@@ -72,19 +72,6 @@ k_group_from64(const double2* __restrict__ src, typename SD::pair* __restrict__ 
     }
 }
 
-// Workgroups are handed to the eight XCDs round robin (workgroup b on XCD b % 8),
-// and each XCD has its own L2.  Site block it (in the order the workgroups are
-// issued) is therefore remapped so that XCD x works through one contiguous eighth
-// of the lattice: the z and t neighbours a site block reads were then most likely
-// fetched into the same L2 by the workgroups just before it.  A bijection of
-// [0, nsb): the first 8*(nsb/8) blocks split into eight contiguous chunks, the
-// remainder stays in place.
-__device__ __forceinline__ int xcd_block(int it, int nsb) {
-    const int q8 = nsb >> 3;
-    if (it >= (q8 << 3)) return it;
-    return (it & 7) * q8 + (it >> 3);
-}
-
 // Epilogues of the hop.
 enum { EPI_PLAIN = 0, EPI_MASS = 1, EPI_MASS_DOT = 2 };
 
@@ -174,8 +161,10 @@ k_hop(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
         gacc.zero();
         for (int e = threadIdx.x; e < rows * (NB + 1); e += 256) tile[e] = C2<E>{(E)0, (E)0};
     }
+    const int bps = blocks_per_slice(g, spb);
     for (int it = blockIdx.x; it < nsb; it += gridDim.x) {
-        const int sb = xcd_block(it, nsb);
+        int sb, tg_unused;
+        xcd_task(it, nsb, 1, bps, sb, tg_unused);
         const int i0 = sb * spb + lane_site;
         const bool live = i0 < g.Vh;
         const int i = live ? i0 : g.Vh - 1;
@@ -291,8 +280,8 @@ k_hop_ls(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
     const int sgn = 4 / tpw;                        // blocks of 16 sites per workgroup
     const int nsb = (g.Vh + 16 * sgn - 1) / (16 * sgn);
     const int ntg = (ntiles + tpw - 1) / tpw;       // tile groups
-    const int task = xcd_block(blockIdx.x, nsb * ntg);
-    const int sb = task / ntg, tg = task - sb * ntg;
+    int sb, tg;
+    xcd_task(blockIdx.x, nsb, ntg, blocks_per_slice(g, 16 * sgn), sb, tg);
     const int tile_w = tg * tpw + w % tpw;
     const bool tile_ok = tile_w < ntiles;
     const int r0 = (tile_ok ? tile_w : ntiles - 1) * TR;

@@ -28,6 +28,9 @@ __device__ __forceinline__ Z2 gld(const double2* p) {
 }
 __device__ __forceinline__ void gst(double2* p, Z2 v) { *p = make_double2(v.re, v.im); }
 
+// a third N x N LDS buffer (the old C in k_small2) fits for N <= 32
+__host__ __device__ constexpr bool small_has_cold(int N) { return N <= 32; }
+
 // A <- (M + M^H)/2 for the leading N x N block of a global [64][64] matrix
 __device__ void load_herm(Z2* A, const double2* M, int N) {
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
@@ -186,6 +189,40 @@ __device__ bool gj_inverse_hpd(Z2* A, int N, Z2* rowk, Z2* colk) {
     return true;
 }
 
+// The same Gauss-Jordan elimination with two buffers: step k reads X and writes Y
+// (then the roles swap), every thread forming its own pivot-row and pivot-column
+// factors, so one barrier per step.  Identical arithmetic to gj_inverse_hpd.
+// Returns the buffer holding the inverse; ok = false on a non-positive pivot.
+__device__ Z2* gj_inverse_hpd_pp(Z2* X, Z2* Y, int N, bool& ok) {
+    __syncthreads();
+    for (int k = 0; k < N; ++k) {
+        const double p = X[k * N + k].re;
+        if (!(p > 0.0) || !isfinite(p)) {
+            ok = false;
+            return X;
+        }
+        const double pinv = 1.0 / p;
+        for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+            const int i = e / N, j = e % N;
+            const Z2 xkj = (j == k) ? Z2{1.0, 0.0} : X[k * N + j];
+            const Z2 rk{xkj.re * pinv, xkj.im * pinv};
+            if (i == k) {
+                Y[e] = rk;
+            } else {
+                const Z2 base = (j == k) ? Z2{0.0, 0.0} : X[e];
+                const Z2 q = zmul(X[i * N + k], rk);
+                Y[e] = Z2{base.re - q.re, base.im - q.im};
+            }
+        }
+        __syncthreads();
+        Z2* t = X;
+        X = Y;
+        Y = t;
+    }
+    ok = true;
+    return X;
+}
+
 // relres[i] = sqrt((C^H H C)_ii) / bnorm[i].  A group of G lanes (G = 16, 32 or
 // 64, the smallest power of two >= N) handles one column i, lane m forming
 // conj(C[m][i]) (H C)[m][i]; the group sums its lanes with shuffles.
@@ -298,24 +335,41 @@ k_small1(const double2* __restrict__ G, const double2* __restrict__ C, double2* 
     __shared__ Z2 rowk[MAXN], colk[MAXN];
     load_herm(A, G, N);
     load_mat(Cm, C, N);
-    if (!gj_inverse_hpd(A, N, rowk, colk)) {
+    bool ok;
+    Z2* Bi;  // G^{-1}
+    if (small_has_cold(N)) {
+        Bi = gj_inverse_hpd_pp(A, sm + 2 * N * N, N, ok);
+    } else {
+        ok = gj_inverse_hpd(A, N, rowk, colk);
+        Bi = A;
+    }
+    if (!ok) {
         if (threadIdx.x == 0) {
             st->halt = 1;
             st->reason = HALT_BREAKDOWN_G;
         }
         return;
     }
+    // beta is Hermitian: average the two triangles the elimination produced
+    Z2 bv[4];   // N*N / blockDim <= 4 (the launcher guarantees it)
+    int cnt = 0;
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x, ++cnt) {
+        const int i = e / N, j = e % N;
+        const Z2 a = Bi[e], b = Bi[j * N + i];
+        bv[cnt] = Z2{0.5 * (a.re + b.re), 0.5 * (a.im - b.im)};
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x, ++cnt) {
+        Bi[e] = bv[cnt];
+        gst(beta + (e / N) * MAXN + e % N, bv[cnt]);
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
         const int i = e / N, j = e % N;
-        // beta is Hermitian: average the two triangles the elimination produced
-        const Z2 a = A[e], b = A[j * N + i];
-        const Z2 bij{0.5 * (a.re + b.re), 0.5 * (a.im - b.im)};
-        gst(beta + i * MAXN + j, bij);
         Z2 s{0.0, 0.0};
         for (int m = 0; m <= j; ++m) {   // C upper triangular
-            const Z2 am = A[i * N + m], bm = A[m * N + i];
-            const Z2 bim{0.5 * (am.re + bm.re), 0.5 * (am.im - bm.im)};
-            const Z2 p = zmul(bim, Cm[m * N + j]);
+            const Z2 p = zmul(Bi[i * N + m], Cm[m * N + j]);
             s.re += p.re;
             s.im += p.im;
         }
@@ -337,6 +391,7 @@ k_small2(const double2* __restrict__ H, double2* __restrict__ C, double2* __rest
     __shared__ int decision;
     load_herm(A, H, N);
     load_mat(W, C, N);
+    if (small_has_cold(N)) load_mat(sm + 2 * N * N, C, N);
     __syncthreads();
     residual_norms(A, W, N, st->bnorm, rel);
     __syncthreads();
@@ -369,14 +424,18 @@ k_small2(const double2* __restrict__ H, double2* __restrict__ C, double2* __rest
         return;
     }
     // C <- S C with S = L^H upper: (S C)[i][j] = sum_{m=i..j} conj(L[m][i]) C[m][j];
-    // the old C is read from global memory, all reads finish before the writes
-    Z2 cn[4];   // N*N / blockDim <= 4 (N <= 16 with 256 threads, N <= 64 with 1024)
+    // the old C is read from its LDS copy when the third buffer fits (N <= 32),
+    // else from global memory; all reads finish before the writes
+    const bool cl = small_has_cold(N);
+    const Z2* Cold = sm + 2 * N * N;
+    Z2 cn[4];   // N*N / blockDim <= 4 (the launcher guarantees it)
     int cnt = 0;
     for (int e = threadIdx.x; e < N * N; e += blockDim.x, ++cnt) {
         const int i = e / N, j = e % N;
         Z2 s2{0.0, 0.0};
         for (int m = i; m <= j; ++m) {
-            const Z2 p = zmul(zconj(A[m * N + i]), gld(C + m * MAXN + j));
+            const Z2 c = cl ? Cold[m * N + j] : gld(C + m * MAXN + j);
+            const Z2 p = zmul(zconj(A[m * N + i]), c);
             s2.re += p.re;
             s2.im += p.im;
         }
@@ -479,10 +538,10 @@ k_small_ru(const double2* __restrict__ H, double2* __restrict__ C, double2* __re
 }
 
 // ---------------------------------------------------------------------------------------------
-static size_t small_lds(int N) { return 2 * (size_t)N * N * sizeof(Z2); }
+static size_t small_lds(int N) { return (small_has_cold(N) ? 3 : 2) * (size_t)N * N * sizeof(Z2); }
 
 hipError_t small_setup() {
-    const int bytes = (int)small_lds(MAXN);
+    const int bytes = (int)(small_lds(32) > small_lds(MAXN) ? small_lds(32) : small_lds(MAXN));
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void*)k_small_init, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
     if ((e = hipFuncSetAttribute((const void*)k_small1, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;

@@ -300,3 +300,22 @@ def test_small_kernel_threads_match_oracle(n, threads):
     ctx.set_option("small_threads", threads)
     X3, _ = ctx.solve(to_dev(B), raise_on_error=False)
     assert col_rel_err(X3.cpu().numpy(), Xo).max() <= 1e-10
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("dims", [(8, 8, 8, 6), (6, 6, 6, 8), (4, 8, 8, 8)])
+def test_site_orders_match_oracle(order, dims):
+    """Slab and lexicographic workgroup orders cover every site exactly once: the
+    operator and the first iterates match the oracle for lattices whose time slice
+    is and is not a whole number of eight-way blocks."""
+    n = 6
+    fat, lng, B = inputs(dims, True, n, 7200 + dims[0])
+    m = 0.15
+    op = oracle.Operator(dims, fat, lng, m)
+    Xo, _ = oracle.block_cg_rq(op.apply, B, 1e-14, max_iter=3)
+    for prec, tol_x in (("fp64", 1e-10), ("fp32", 1e-4)):
+        ctx = context(dims, True, fat, lng, m, tol=1e-14, ru_delta=0.0, max_iter=3, prec=prec)
+        ctx.set_option("site_order", order)
+        assert col_rel_err(ctx.apply(to_dev(B)).cpu().numpy(), op.apply(B)).max() <= 1e-12
+        X3, _ = ctx.solve(to_dev(B), raise_on_error=False)
+        assert col_rel_err(X3.cpu().numpy(), Xo).max() <= tol_x
