@@ -96,6 +96,10 @@ def main():
     ap.add_argument("--nrhs", type=int, default=16)
     ap.add_argument("--prec", default=None, help="storage precision override (fp64/fp32/fp16/bf16)")
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--sweep", default=None,
+                    help="comma-separated N list: per-kernel GB/s of the 32^3x64 block iteration vs N "
+                         "(a few iterations per N, FP32 storage unless --prec), one JSON line")
+    ap.add_argument("--sweep-iters", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device three times (the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to HBM bytes)")
@@ -111,6 +115,9 @@ def main():
     import torch
 
     from paper_1710_09745_amd import bcg, synth
+
+    if args.sweep:
+        return sweep(args, bcg, synth, torch)
 
     if args.workload == "config2":
         c = synth.CONFIGS[2]
@@ -243,6 +250,55 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def sweep(args, bcg, synth, torch):
+    """Kernel GB/s of the block iteration vs N on the 32^3x64 lattice: each N runs
+    a fixed number of block iterations (reliable updates off, so every iteration
+    does the same work) with every kernel class timed by HIP events."""
+    c = synth.CONFIGS[3]
+    dims, m = c["dims"], c["mass"]
+    prec = args.prec or "fp32"
+    fat, lng, _ = synth.config_inputs(3, nrhs=1)
+    Vh = synth.volume(dims) // 2
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = bcg.Context(dims, improved=True, device=dev)
+    ctx.load_links(fat, lng)
+    ctx.set_mass(m)
+    rows = []
+    for N in [int(x) for x in args.sweep.split(",")]:
+        B = synth.rhs(synth.make_rng(7), N, dims)
+        Bt = torch.from_numpy(B).to(dev)
+        ctx.set_solver(tol=1e-14, max_iter=args.sweep_iters, prec=prec, ru_delta=0.0)
+        ctx.solve(Bt, raise_on_error=False)                      # warm (buffers, links)
+        ctx.set_profiling(bcg.KERNELS)
+        ctx.profile_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.solve(Bt, raise_on_error=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ctx.set_profiling([])
+        row = {"nrhs": N, "iters": args.sweep_iters, "solve_ms": round(wall * 1e3, 3)}
+        for k in ("hop_oe", "hop_eo", "pass_a", "pass_b", "gram"):
+            n, ms = ctx.kernel_time(k)
+            if not n:
+                continue
+            t = ms / n
+            if k == "gram":
+                # one non-aliased (P^H AP) and one aliased (Qt^H Qt) Gram per iteration
+                b = 0.5 * (model_bytes_per_site(k, N, prec) + model_bytes_per_site(k, N, prec, aliased_gram=True)) * Vh
+            else:
+                b = model_bytes_per_site(k, N, prec) * Vh
+            row[k] = {"us": round(t * 1e3, 1), "GB/s": round(b / (t * 1e-3) / 1e9, 1),
+                      "frac_hbm": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        rows.append(row)
+        print(f"[sweep] N={N}: " + json.dumps(row), file=sys.stderr, flush=True)
+        del Bt
+    print(json.dumps({"metric": "block-iteration kernel GB/s vs N (32^3x64 improved staggered)",
+                      "storage": prec, "dims": list(dims), "rows": rows}), flush=True)
     ctx.close()
 
 

@@ -109,6 +109,16 @@ __device__ __forceinline__ void xcd_task(int b, int nsb, int ntg, int bps, int& 
     tg = b - sb * ntg;
 }
 
+// Column-tile-major order: every site block of tile group 0, then of tile group 1,
+// ... (one sweep over the lattice per group of columns, each sweep in the slab
+// order above), so the stencil window of one sweep is a group's columns only.
+__device__ __forceinline__ void xcd_task_tm(int b, int nsb, int ntg, int bps, int& sb, int& tg) {
+    tg = b / nsb;
+    int unused;
+    xcd_task(b - tg * nsb, nsb, 1, bps, sb, unused);
+    (void)ntg;
+}
+
 // site blocks of spb sites per time slice, or 0 when a slice is not a whole number of blocks
 __host__ __device__ inline int blocks_per_slice(const Geom& g, int spb) {
     if (!g.slab) return 0;

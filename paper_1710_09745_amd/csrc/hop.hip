@@ -102,7 +102,7 @@ __device__ __forceinline__ void hop_fetch(HopOperands<S, TR>& o, int k, int j, i
     const unsigned nb = (unsigned)nbl >> 1;
     const rsrc_t wr = make_rsrc(Wb + (size_t)k * 9 * plane);
     const rsrc_t wsr = S::scaled ? make_rsrc(Wsb + (size_t)k * Vh) : wr;
-    buf_group<S, 9, AUX_NT>(wr, wsr, site_vo, site_so, plane, o.w);
+    buf_group<S, 9, AUX_NONE>(wr, wsr, site_vo, site_so, plane, o.w);
 #pragma unroll
     for (int r = 0; r < TR; ++r) buf_group<S, 3, AUX_NONE>(vin[r], vins[r], nb * S::bytes, nb * 4u, plane, o.v[r]);
 }
@@ -138,7 +138,7 @@ k_hop(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
       const typename S::pair* __restrict__ in, const float* __restrict__ ins,
       typename S::pair* __restrict__ out, float* __restrict__ outs,
       const typename S::pair* __restrict__ ctr, const float* __restrict__ ctrs,
-      double m2d, int N, Geom g, int out_parity, int spb, const int* __restrict__ halt,
+      double m2d, int N, Geom g, int out_parity, int spb, int ntg, const int* __restrict__ halt,
       double* __restrict__ dot, double2* __restrict__ partials) {
     using R = typename S::real;
     using E = typename TileElem<S>::type;
@@ -162,9 +162,11 @@ k_hop(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
         for (int e = threadIdx.x; e < rows * (NB + 1); e += 256) tile[e] = C2<E>{(E)0, (E)0};
     }
     const int bps = blocks_per_slice(g, spb);
-    for (int it = blockIdx.x; it < nsb; it += gridDim.x) {
-        int sb, tg_unused;
-        xcd_task(it, nsb, 1, bps, sb, tg_unused);
+    const int gcols = tpb * TR;  // columns of one tile group
+    for (int it = blockIdx.x; it < nsb * ntg; it += gridDim.x) {
+        int sb, tg;
+        xcd_task_tm(it, nsb, ntg, bps, sb, tg);
+        const int cend = (ntg == 1) ? N : min(N, (tg + 1) * gcols);
         const int i0 = sb * spb + lane_site;
         const bool live = i0 < g.Vh;
         const int i = live ? i0 : g.Vh - 1;
@@ -173,7 +175,7 @@ k_hop(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
         site_coords(g, i, out_parity, x);
         const int lex = x[0] + g.L[0] * (x[1] + g.L[1] * (x[2] + g.L[2] * x[3]));
         const unsigned site_vo = (unsigned)i * S::bytes, site_so = (unsigned)i * 4u;
-        for (int r0 = grp * TR; r0 < N; r0 += tpb * TR) {
+        for (int r0 = tg * gcols + grp * TR; r0 < cend; r0 += gcols) {
             rsrc_t vin[TR], vins[TR];
 #pragma unroll
             for (int r = 0; r < TR; ++r) {
@@ -281,7 +283,7 @@ k_hop_ls(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
     const int nsb = (g.Vh + 16 * sgn - 1) / (16 * sgn);
     const int ntg = (ntiles + tpw - 1) / tpw;       // tile groups
     int sb, tg;
-    xcd_task(blockIdx.x, nsb, ntg, blocks_per_slice(g, 16 * sgn), sb, tg);
+    xcd_task_tm(blockIdx.x, nsb, ntg, blocks_per_slice(g, 16 * sgn), sb, tg);
     const int tile_w = tg * tpw + w % tpw;
     const bool tile_ok = tile_w < ntiles;
     const int r0 = (tile_ok ? tile_w : ntiles - 1) * TR;
@@ -323,7 +325,7 @@ k_hop_ls(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
         if (v < 0) nbl += wrap;
         const unsigned nb = (unsigned)nbl >> 1;
         const unsigned k = (unsigned)(mu * NJ + j);
-        buf_group<S, 9, AUX_NT>(wr, wsr, (k * 9u * (unsigned)Vh + (unsigned)i) * S::bytes,
+        buf_group<S, 9, AUX_NONE>(wr, wsr, (k * 9u * (unsigned)Vh + (unsigned)i) * S::bytes,
                                 (k * (unsigned)Vh + (unsigned)i) * 4u, plane, o.w);
 #pragma unroll
         for (int r = 0; r < TR; ++r) buf_group<S, 3, AUX_NONE>(vin[r], vins[r], nb * S::bytes, nb * 4u, plane, o.v[r]);
@@ -416,12 +418,10 @@ hipError_t links_from64(Prec pd, const void* W64, void* Wd, int nl, long Vh, hip
 }
 
 HopShape hop_shape(Prec p, int N, int tr, int tpb, int pf, int kernel, const Geom& g, bool fused) {
-    (void)p;
     HopShape h;
-    // default kernel: the site-parallel kernel (two lane groups of eight right-hand
-    // sides share a workgroup's sites) when its grid fills the chip four times
-    // over, the lane-split kernel on smaller lattices (measured on MI355X: 16^4 and
-    // 32^3 x 64 at N = 4 ... 64)
+    // default kernel: the site-parallel kernel when its grid fills the chip four
+    // times over, the lane-split kernel on smaller lattices (measured on MI355X:
+    // 16^4 and 32^3 x 64 at N = 4 ... 64)
     const bool small_lattice = g.Vh / 128 < 4 * 256;
     if (fused) h.split = 0;
     else if (kernel == 1) h.split = 1;
@@ -435,11 +435,17 @@ HopShape hop_shape(Prec p, int N, int tr, int tpb, int pf, int kernel, const Geo
         if (N <= 1) h.tr = 1;
         return h;
     }
-    if (N <= 1) { h.tr = 1; h.tpb = 1; h.pf = 1; }
-    else if (N <= 2) { h.tr = 2; h.tpb = 1; h.pf = 1; }
-    else if (N <= 4) { h.tr = 4; h.tpb = 1; h.pf = 1; }
-    else if (N <= 8) { h.tr = 4; h.tpb = 2; h.pf = 1; }
-    else { h.tr = 8; h.tpb = 2; h.pf = 1; }
+    // site-parallel: register tile TR and lane groups tpb by N; a workgroup covers
+    // tpb x TR columns and N > 16 takes several sweeps over the lattice, one per
+    // group of 16 columns (narrower sweeps re-read the links more often than they
+    // save in neighbour re-fetches: measured slower at 32^3 x 64)
+    (void)p;
+    h.pf = 1;
+    if (N <= 1) { h.tr = 1; h.tpb = 1; }
+    else if (N <= 2) { h.tr = 2; h.tpb = 1; }
+    else if (N <= 4) { h.tr = 4; h.tpb = 1; }
+    else if (N <= 8) { h.tr = 4; h.tpb = 2; }
+    else { h.tr = 8; h.tpb = 2; }
     if (pf == 1) h.pf = 1;
     else if (pf == 2) h.pf = 0;
     if (N > 1 && (tr == 1 || tr == 2 || tr == 4 || tr == 8)) h.tr = tr;
@@ -471,7 +477,8 @@ static void launch_hop_g(const void* W, const void* in, void* out, const void* c
         return S::scaled && p ? (float*)((char*)p + (size_t)S::bytes * cols * K * Vh) : nullptr;
     };
     const int spb = 256 / h.tpb;
-    dim3 grid(hop_grid(g, h, GR));
+    const int ntg = GR ? 1 : (N + h.tpb * TR - 1) / (h.tpb * TR);
+    dim3 grid(GR ? hop_grid(g, h, true) : (unsigned)(((g.Vh + spb - 1) / spb) * ntg));
     const size_t lds = GR ? (size_t)3 * spb * (NB + 1) * sizeof(C2<typename TileElem<S>::type>) : 0;
     float* Ws = scale(W, NL, 9);
     float* ins = scale(in, N, 3);
@@ -480,7 +487,7 @@ static void launch_hop_g(const void* W, const void* in, void* out, const void* c
 #define HOP_GO(E)                                                                                      \
     hipLaunchKernelGGL((k_hop<S, TR, NL, E, PF, NB, GR>), grid, dim3(256), lds, s, (const P*)W, Ws,        \
                        (const P*)in, ins, (P*)out, outs, (const P*)ctr, ctrs, m2, N, g, out_parity, spb, \
-                       halt, dot, partials)
+                       ntg, halt, dot, partials)
     if (epi == EPI_PLAIN) HOP_GO(EPI_PLAIN);
     else if constexpr (!GR) {
         if (epi == EPI_MASS) HOP_GO(EPI_MASS);

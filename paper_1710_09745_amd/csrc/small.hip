@@ -28,7 +28,8 @@ __device__ __forceinline__ Z2 gld(const double2* p) {
 }
 __device__ __forceinline__ void gst(double2* p, Z2 v) { *p = make_double2(v.re, v.im); }
 
-// a third N x N LDS buffer (the old C in k_small2) fits for N <= 32
+// the wide LDS layout (five N x N buffers: the old C in k_small2 and the ping-pong
+// partners of the factorisations) for N <= 32
 __host__ __device__ constexpr bool small_has_cold(int N) { return N <= 32; }
 
 // A <- (M + M^H)/2 for the leading N x N block of a global [64][64] matrix
@@ -157,6 +158,73 @@ __device__ bool chol_inv_lower(Z2* A, Z2* Zm, int N, const double* diag) {
         if (e % N > e / N) A[e] = Z2{0.0, 0.0};
     __syncthreads();
     return true;
+}
+
+// chol_inv_lower with two buffers per matrix: step k reads (X, ZX) and writes
+// (Y, ZY), then the roles swap, every thread forming the scaled column-k factors it
+// needs itself, so one barrier per step.  The same products as chol_inv_lower.
+// On return *L and *Zout point at the buffers holding L (lower, strict upper
+// zeroed) and L^{-1}; ok = false on a breakdown pivot (same rule as chol_lower).
+__device__ void chol_inv_lower_pp(Z2* X, Z2* Y, Z2* ZX, Z2* ZY, int N, const double* diag, bool& ok,
+                                  Z2** L, Z2** Zout) {
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int i = e / N, j = e % N;
+        ZX[e] = Z2{i == j ? 1.0 : 0.0, 0.0};
+    }
+    __syncthreads();
+    for (int k = 0; k < N; ++k) {
+        const double d = X[k * N + k].re;
+        const double floor_k = diag ? 1e-14 * diag[k] : 0.0;
+        if (!(d > floor_k) || !isfinite(d)) {
+            ok = false;
+            *L = X;
+            *Zout = ZX;
+            return;
+        }
+        const double rs = 1.0 / sqrt(d);
+        for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+            const int i = e / N, j = e % N;
+            // L part (lower triangle only; the strict upper triangle is never read)
+            if (j <= i) {
+                Z2 v = X[e];
+                if (j == k) {
+                    v = (i == k) ? Z2{d * rs, 0.0} : Z2{v.re * rs, v.im * rs};
+                } else if (j > k) {
+                    const Z2 a = X[i * N + k], b = X[j * N + k];
+                    const Z2 p = zmul(Z2{a.re * rs, a.im * rs}, zconj(Z2{b.re * rs, b.im * rs}));
+                    v.re -= p.re;
+                    v.im -= p.im;
+                }
+                Y[e] = v;
+            }
+            // Z part: row k scaled, rows below k updated with the scaled row k
+            if (j <= k || j <= i) {
+                Z2 z = ZX[e];
+                if (i == k && j <= k) {
+                    z = Z2{z.re * rs, z.im * rs};
+                } else if (i > k && j <= k) {
+                    const Z2 a = X[i * N + k], zk = ZX[k * N + j];
+                    const Z2 p = zmul(Z2{a.re * rs, a.im * rs}, Z2{zk.re * rs, zk.im * rs});
+                    z.re -= p.re;
+                    z.im -= p.im;
+                }
+                ZY[e] = z;
+            }
+        }
+        __syncthreads();
+        Z2* t = X;
+        X = Y;
+        Y = t;
+        t = ZX;
+        ZX = ZY;
+        ZY = t;
+    }
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x)
+        if (e % N > e / N) X[e] = Z2{0.0, 0.0};
+    __syncthreads();
+    ok = true;
+    *L = X;
+    *Zout = ZX;
 }
 
 // In-place Gauss-Jordan inverse of a Hermitian positive-definite A (no pivoting
@@ -414,8 +482,14 @@ k_small2(const double2* __restrict__ H, double2* __restrict__ C, double2* __rest
     }
     __syncthreads();
     if (decision != HALT_NONE) return;
-    // Cholesky of H and L^{-1} together (W, which held C, becomes L^{-1})
-    if (!chol_inv_lower(A, W, N, nullptr)) {
+    // Cholesky of H and L^{-1} together (W, which held C, becomes L^{-1}; with the
+    // wide LDS layout the ping-pong variant, one barrier per step)
+    Z2* Lm = A;
+    Z2* Zm = W;
+    bool ok;
+    if (small_has_cold(N)) chol_inv_lower_pp(A, sm + 3 * N * N, W, sm + 4 * N * N, N, nullptr, ok, &Lm, &Zm);
+    else ok = chol_inv_lower(A, W, N, nullptr);
+    if (!ok) {
         if (threadIdx.x == 0) {
             st->halt = 1;
             st->reason = HALT_BREAKDOWN_H;
@@ -435,7 +509,7 @@ k_small2(const double2* __restrict__ H, double2* __restrict__ C, double2* __rest
         Z2 s2{0.0, 0.0};
         for (int m = i; m <= j; ++m) {
             const Z2 c = cl ? Cold[m * N + j] : gld(C + m * MAXN + j);
-            const Z2 p = zmul(zconj(A[m * N + i]), c);
+            const Z2 p = zmul(zconj(Lm[m * N + i]), c);
             s2.re += p.re;
             s2.im += p.im;
         }
@@ -447,8 +521,8 @@ k_small2(const double2* __restrict__ H, double2* __restrict__ C, double2* __rest
     // S^H = L; S^{-1} = (L^{-1})^H  (leading N x N blocks only)
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
         const int i = e / N, j = e % N;
-        gst(SH + i * MAXN + j, (j <= i) ? A[i * N + j] : Z2{0.0, 0.0});
-        gst(Sinv + i * MAXN + j, (j >= i) ? zconj(W[j * N + i]) : Z2{0.0, 0.0});
+        gst(SH + i * MAXN + j, (j <= i) ? Lm[i * N + j] : Z2{0.0, 0.0});
+        gst(Sinv + i * MAXN + j, (j >= i) ? zconj(Zm[j * N + i]) : Z2{0.0, 0.0});
     }
     if (threadIdx.x == 0) st->pb_mode = PB_FULL;
 }
@@ -538,7 +612,7 @@ k_small_ru(const double2* __restrict__ H, double2* __restrict__ C, double2* __re
 }
 
 // ---------------------------------------------------------------------------------------------
-static size_t small_lds(int N) { return (small_has_cold(N) ? 3 : 2) * (size_t)N * N * sizeof(Z2); }
+static size_t small_lds(int N) { return (small_has_cold(N) ? 5 : 2) * (size_t)N * N * sizeof(Z2); }
 
 hipError_t small_setup() {
     const int bytes = (int)(small_lds(32) > small_lds(MAXN) ? small_lds(32) : small_lds(MAXN));
