@@ -562,9 +562,90 @@ static void pass_a_t(void* Q, const void* AP, const double2* beta, int N, int Vh
     else pass_a_nb<S, 4>(Q, AP, beta, N, Vh, halt, partials, bps, s);
 }
 
+// Pass A on the matrix cores (FP32 / FP64 storage, 16 < N <= 32), the same
+// transposed-tile scheme as pass B: Qt^T[j][r] = Q^T[j][r] - sum_l beta^T[j][l] AP^T[l][r]
+// with beta (Hermitian, staged in LDS) as the A operand and 16 rows of AP as the
+// B operand, FP64 products.
+template <typename S, int NT>
+__global__ void __launch_bounds__(256)
+k_pass_a_mfma(typename S::pair* __restrict__ Q, const typename S::pair* __restrict__ AP,
+              const double2* __restrict__ beta, int N, int Vh, const int* __restrict__ halt) {
+    using PR = typename S::pair;
+    using R = typename S::real;
+    constexpr int NQ = 4 * NT;
+    constexpr int NP = 16 * NT;
+    extern __shared__ double2 cf[];  // [NP][NP] beta, zero outside N x N
+    if (halt != nullptr && *halt) return;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r16 = lane & 15, k4 = lane >> 4;
+    for (int e = threadIdx.x; e < NP * NP; e += 256) {
+        const int l = e / NP, j = e % NP;
+        cf[e] = (l < N && j < N) ? beta[l * MAXN + j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const long nrb = (long)((Vh + 15) / 16) * 3;
+    const long ngroups = (nrb + 3) / 4;
+    for (long g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const long rb0 = g * 4 + w;
+        const bool rb_ok = rb0 < nrb;
+        const long rb = rb_ok ? rb0 : nrb - 1;
+        const int c = (int)(rb % 3);
+        const int site = (int)(rb / 3) * 16 + r16;
+        const bool live = rb_ok && site < Vh;
+        const int si = site < Vh ? site : Vh - 1;
+        R ar[NQ], ai[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int l = 4 * q + k4;
+            const bool ok = l < N;
+            const PR a = AP[((long)(ok ? l : N - 1) * 3 + c) * Vh + si];
+            ar[q] = ok ? a.x : (R)0;
+            ai[q] = ok ? a.y : (R)0;
+        }
+#pragma unroll 1
+        for (int jt = 0; jt < NT; ++jt) {
+            const int jo = jt * 16 + r16;
+            dvec4 yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int l = 4 * q + k4;
+                const double2 m = cf[l * NP + jo];
+                const double dr = (double)ar[q], di = (double)ai[q];
+                yr = __builtin_amdgcn_mfma_f64_16x16x4f64(m.x, dr, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f64_16x16x4f64(m.x, di, yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-m.y, di, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f64_16x16x4f64(m.y, dr, yi, 0, 0, 0);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int j = jt * 16 + 4 * m + k4;
+                if (!live || j >= N) continue;
+                const long o = ((long)j * 3 + c) * Vh + site;
+                PR qv = Q[o];
+                qv.x = (R)((double)qv.x - yr[m]);
+                qv.y = (R)((double)qv.y - yi[m]);
+                Q[o] = qv;
+            }
+        }
+    }
+}
+
 hipError_t launch_pass_a(Prec prec, void* Q, const void* AP, const double2* beta, int N, int Vh,
-                         const int* halt, double2* partials, int cpt, int bps, hipStream_t s) {
+                         const int* halt, double2* partials, int cpt, int bps, bool mfma, hipStream_t s) {
     if (partials != nullptr && fused_tile_bytes(prec, N) == 0) return hipErrorInvalidValue;
+    if (mfma && partials == nullptr && N > 16 && N <= 32 && (prec == Prec::FP64 || prec == Prec::FP32)) {
+        const long groups = ((long)((Vh + 15) / 16) * 3 + 3) / 4;
+        const dim3 grid((unsigned)(groups < 2048 ? groups : 2048));
+        const size_t lds = (size_t)32 * 32 * sizeof(double2);
+        if (prec == Prec::FP64)
+            hipLaunchKernelGGL((k_pass_a_mfma<F64, 2>), grid, dim3(256), lds, s, (double2*)Q, (const double2*)AP,
+                               beta, N, Vh, halt);
+        else
+            hipLaunchKernelGGL((k_pass_a_mfma<F32, 2>), grid, dim3(256), lds, s, (float2*)Q, (const float2*)AP,
+                               beta, N, Vh, halt);
+        return hipGetLastError();
+    }
     switch (prec) {
         case Prec::FP64: pass_a_t<F64>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, s); break;
         case Prec::FP32: pass_a_t<F32>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, s); break;
@@ -753,10 +834,164 @@ static void pass_b_t(double2* X, const void* Qt, const void* P, void* Qn, void* 
     else pass_b_nb<S, 4>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, bps, s);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Pass B on the matrix cores (FP32 and FP64 storage, N > 16).  Transposed, every
+// output column tile is a small GEMM  Y^T[j][r] = sum_l M^T[j][l] D^T[l][r]  with a
+// coefficient matrix M (beta C, S^{-1} or S^H) as the 16 x 4 A operand and the data
+// (P or Qt over a block of 16 rows: 16 consecutive sites of one colour) as the
+// 4 x 16 B operand, in FP64 (v_mfma_f64_16x16x4f64; a complex product is four real
+// ones).  A wave owns one row block: it loads all N columns of P and Qt for its rows
+// once (each load: 4 columns x 16 consecutive sites) into registers and then walks
+// the NT output column tiles.  Accumulator element m of lane l is column 4m + l/16
+// of the tile at row l % 16, so each store also covers 4 columns x 16 sites.  S^{-1}
+// is upper and S^H lower triangular: K-steps wholly outside a triangle are skipped.
+// Coefficients beyond N x N are treated as zero (their storage is never written).
+// ---------------------------------------------------------------------------------------------
+template <typename S, int NT>
+__global__ void __launch_bounds__(256)
+k_pass_b_mfma(double2* __restrict__ X, const typename S::pair* __restrict__ Qt,
+              const typename S::pair* __restrict__ P, typename S::pair* __restrict__ Qn,
+              typename S::pair* __restrict__ Pn, const double2* __restrict__ betaC,
+              const double2* __restrict__ Sinv, const double2* __restrict__ SH, int N, int Vh,
+              const SolveState* __restrict__ stt) {
+    using PR = typename S::pair;
+    using R = typename S::real;
+    constexpr int NQ = 4 * NT;      // K-steps of four columns
+    constexpr int NP = 16 * NT;     // N padded to whole tiles
+    extern __shared__ double2 cf[];  // [3][NP][NP] coefficient matrices, zero outside N x N
+    const int mode = stt->pb_mode;
+    if (mode == PB_SKIP) return;
+    const bool full = (mode == PB_FULL);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r16 = lane & 15, k4 = lane >> 4;
+    for (int e = threadIdx.x; e < 3 * NP * NP; e += 256) {
+        const int mat = e / (NP * NP), rem = e - mat * NP * NP;
+        const int l = rem / NP, j = rem % NP;
+        const double2* M = mat == 0 ? betaC : (mat == 1 ? Sinv : SH);
+        cf[e] = (l < N && j < N) ? M[l * MAXN + j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const long nrb = (long)((Vh + 15) / 16) * 3;
+    const long ngroups = (nrb + 3) / 4;
+    for (long g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const long rb0 = g * 4 + w;
+        const bool rb_ok = rb0 < nrb;
+        const long rb = rb_ok ? rb0 : nrb - 1;
+        const int c = (int)(rb % 3);
+        const int site = (int)(rb / 3) * 16 + r16;
+        const bool live = rb_ok && site < Vh;
+        const int si = site < Vh ? site : Vh - 1;
+        // lane (r16, k4) holds column 4q + k4 of row (site, c) for every K-step q
+        R pr[NQ], pi[NQ], qr[NQ], qi[NQ];  // storage precision; exact in FP64 at use
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int l = 4 * q + k4;
+            const bool ok = l < N;
+            const int lc = ok ? l : N - 1;
+            const PR a = P[((long)lc * 3 + c) * Vh + si];
+            const PR b = Qt[((long)lc * 3 + c) * Vh + si];
+            pr[q] = ok ? a.x : (R)0;
+            pi[q] = ok ? a.y : (R)0;
+            qr[q] = ok ? b.x : (R)0;
+            qi[q] = ok ? b.y : (R)0;
+        }
+#pragma unroll 1
+        for (int jt = 0; jt < NT; ++jt) {
+            const int jo = jt * 16 + r16;  // coefficient column of this lane (A-operand row)
+            dvec4 xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0};
+            dvec4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};  // Qt S^{-1}
+            dvec4 br = {0, 0, 0, 0}, bi = {0, 0, 0, 0};  // P S^H
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int l = 4 * q + k4;
+                const double dpr = (double)pr[q], dpi = (double)pi[q];
+                const double dqr = (double)qr[q], dqi = (double)qi[q];
+                const double2 m1 = cf[(0 * NP + l) * NP + jo];
+                const bool uq = full && q <= 4 * jt + 3;
+                const bool up = full && q >= 4 * jt;
+                const double2 m2 = uq ? cf[(1 * NP + l) * NP + jo] : make_double2(0.0, 0.0);
+                const double2 m3 = up ? cf[(2 * NP + l) * NP + jo] : make_double2(0.0, 0.0);
+                // independent accumulators interleaved between the two halves of each product
+                xr = __builtin_amdgcn_mfma_f64_16x16x4f64(m1.x, dpr, xr, 0, 0, 0);
+                xi = __builtin_amdgcn_mfma_f64_16x16x4f64(m1.x, dpi, xi, 0, 0, 0);
+                if (uq) {
+                    ar = __builtin_amdgcn_mfma_f64_16x16x4f64(m2.x, dqr, ar, 0, 0, 0);
+                    ai = __builtin_amdgcn_mfma_f64_16x16x4f64(m2.x, dqi, ai, 0, 0, 0);
+                }
+                if (up) {
+                    br = __builtin_amdgcn_mfma_f64_16x16x4f64(m3.x, dpr, br, 0, 0, 0);
+                    bi = __builtin_amdgcn_mfma_f64_16x16x4f64(m3.x, dpi, bi, 0, 0, 0);
+                }
+                xr = __builtin_amdgcn_mfma_f64_16x16x4f64(-m1.y, dpi, xr, 0, 0, 0);
+                xi = __builtin_amdgcn_mfma_f64_16x16x4f64(m1.y, dpr, xi, 0, 0, 0);
+                if (uq) {
+                    ar = __builtin_amdgcn_mfma_f64_16x16x4f64(-m2.y, dqi, ar, 0, 0, 0);
+                    ai = __builtin_amdgcn_mfma_f64_16x16x4f64(m2.y, dqr, ai, 0, 0, 0);
+                }
+                if (up) {
+                    br = __builtin_amdgcn_mfma_f64_16x16x4f64(-m3.y, dpi, br, 0, 0, 0);
+                    bi = __builtin_amdgcn_mfma_f64_16x16x4f64(m3.y, dpr, bi, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int j = jt * 16 + 4 * m + k4;
+                if (!live || j >= N) continue;
+                const long o = ((long)j * 3 + c) * Vh + site;
+                double2 xv = X[o];
+                xv.x += xr[m];
+                xv.y += xi[m];
+                X[o] = xv;
+                if (full) {
+                    PR qv, pv;
+                    qv.x = (R)ar[m];
+                    qv.y = (R)ai[m];
+                    // P = Q + P S^H with Q as stored
+                    pv.x = (R)((double)qv.x + br[m]);
+                    pv.y = (R)((double)qv.y + bi[m]);
+                    Qn[o] = qv;
+                    Pn[o] = pv;
+                }
+            }
+        }
+    }
+}
+
+// matrix-core pass B applies (FP32 / FP64 storage, no fused Gram, 16 < N <= 32:
+// all three coefficient matrices fit in LDS; measured 1.4x faster than the vector
+// kernel at N = 32 on 32^3 x 64, while at N = 64 the per-tile staging makes it slower)
+static bool pass_b_mfma_ok(Prec prec, int N, bool fused) {
+    return !fused && N > 16 && N <= 32 && (prec == Prec::FP64 || prec == Prec::FP32);
+}
+
+template <typename S>
+static void pass_b_mfma_t(double2* X, const void* Qt, const void* P, void* Qn, void* Pn, const double2* betaC,
+                          const double2* Sinv, const double2* SH, int N, int Vh, const SolveState* st,
+                          hipStream_t s) {
+    using PP = typename S::pair;
+    const long nrb = (long)((Vh + 15) / 16) * 3;
+    const long groups = (nrb + 3) / 4;
+    // persistent over groups of four row blocks: the staged coefficients are reused
+    const dim3 grid((unsigned)(groups < 2048 ? groups : 2048));
+#define PBM(T)                                                                                          \
+    hipLaunchKernelGGL((k_pass_b_mfma<S, T>), grid, dim3(256),                                          \
+                       (size_t)3 * (16 * T) * (16 * T) * sizeof(double2), s, X,                        \
+                       (const PP*)Qt, (const PP*)P, (PP*)Qn, (PP*)Pn, betaC, Sinv, SH, N, Vh, st)
+    PBM(2);
+#undef PBM
+}
+
 hipError_t launch_pass_b(Prec prec, double2* X, const void* Qt, const void* P, void* Qn, void* Pn,
                          const double2* betaC, const double2* Sinv, const double2* SH, int N,
-                         int Vh, const SolveState* state, double2* partials, int cpt, int bps, hipStream_t s) {
+                         int Vh, const SolveState* state, double2* partials, int cpt, int bps, bool mfma,
+                         hipStream_t s) {
     if (partials != nullptr && fused_tile_bytes(prec, N) == 0) return hipErrorInvalidValue;
+    if (mfma && pass_b_mfma_ok(prec, N, partials != nullptr)) {
+        if (prec == Prec::FP64) pass_b_mfma_t<F64>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, s);
+        else pass_b_mfma_t<F32>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, s);
+        return hipGetLastError();
+    }
     switch (prec) {
         case Prec::FP64: pass_b_t<F64>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, s); break;
         case Prec::FP32: pass_b_t<F32>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, s); break;

@@ -319,3 +319,24 @@ def test_site_orders_match_oracle(order, dims):
         assert col_rel_err(ctx.apply(to_dev(B)).cpu().numpy(), op.apply(B)).max() <= 1e-12
         X3, _ = ctx.solve(to_dev(B), raise_on_error=False)
         assert col_rel_err(X3.cpu().numpy(), Xo).max() <= tol_x
+
+
+@pytest.mark.parametrize("n", [17, 32, 40, 64])
+def test_pass_kernels_match_oracle(n):
+    """Matrix-core (FP64 MFMA, transposed column tiles, triangular K-steps skipped;
+    used for 16 < N <= 32) and vector-ALU passes A and B give the oracle's iterates,
+    FP64 and FP32 storage."""
+    dims = (6, 6, 6, 8)
+    fat, lng, B = inputs(dims, True, n, 7300 + n)
+    m = 0.15
+    op = oracle.Operator(dims, fat, lng, m)
+    Xo, _ = oracle.block_cg_rq(op.apply, B, 1e-14, max_iter=3)
+    for prec, tol_x in (("fp64", 1e-10), ("fp32", 1e-4)):
+        for kernel in (1, 2):
+            ctx = context(dims, True, fat, lng, m, tol=1e-14, ru_delta=0.0, max_iter=3, prec=prec)
+            ctx.set_option("pass_kernel", kernel)
+            X3, _ = ctx.solve(to_dev(B), raise_on_error=False)
+            assert col_rel_err(X3.cpu().numpy(), Xo).max() <= tol_x, f"{prec} pass_kernel={kernel}"
+    ctx = context(dims, True, fat, lng, m, tol=1e-8, prec="fp32")
+    X, info = ctx.solve(to_dev(B))
+    assert true_rel_res(op, B, X.cpu().numpy()).max() <= 1e-8
