@@ -961,6 +961,8 @@ k_pass_b_mfma(double2* __restrict__ X, const typename S::pair* __restrict__ Qt,
 // matrix-core pass B applies (FP32 / FP64 storage, no fused Gram, 16 < N <= 32:
 // all three coefficient matrices fit in LDS; measured 1.4x faster than the vector
 // kernel at N = 32 on 32^3 x 64, while at N = 64 the per-tile staging makes it slower)
+// (the 16-bit formats stay on the vector kernel: a group's scale spans three
+// colours, and a three-wave matrix-core variant measured no faster at N = 32)
 static bool pass_b_mfma_ok(Prec prec, int N, bool fused) {
     return !fused && N > 16 && N <= 32 && (prec == Prec::FP64 || prec == Prec::FP32);
 }

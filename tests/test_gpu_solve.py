@@ -337,6 +337,9 @@ def test_pass_kernels_match_oracle(n):
             ctx.set_option("pass_kernel", kernel)
             X3, _ = ctx.solve(to_dev(B), raise_on_error=False)
             assert col_rel_err(X3.cpu().numpy(), Xo).max() <= tol_x, f"{prec} pass_kernel={kernel}"
-    ctx = context(dims, True, fat, lng, m, tol=1e-8, prec="fp32")
-    X, info = ctx.solve(to_dev(B))
-    assert true_rel_res(op, B, X.cpu().numpy()).max() <= 1e-8
+    for prec in ("fp32", "fp16", "bf16"):
+        for kernel in (1, 2):
+            ctx = context(dims, True, fat, lng, m, tol=1e-8, prec=prec)
+            ctx.set_option("pass_kernel", kernel)
+            X, info = ctx.solve(to_dev(B))
+            assert true_rel_res(op, B, X.cpu().numpy()).max() <= 1e-8, f"{prec} pass_kernel={kernel}"
