@@ -171,7 +171,11 @@ int bcg_link_force(bcg_ctx *ctx, const void *X, const void *Lam, int nrhs, void 
  *                         x-th eighth of every time slice and all XCDs sweep the
  *                         slices together, 2: plain lexicographic order
  *   BCG_OPT_PASS_KERNEL   1: passes A and B on the matrix cores (FP64 MFMA) for
- *                         16 < N <= 32 in FP32 / FP64 storage, 2: on the vector ALUs
+ *                         16 < N <= 32 in FP32 / FP64 storage, otherwise vector
+ *                         ALUs (pass B with its N x N coefficients staged in LDS);
+ *                         2: vector kernels with LDS-staged coefficients (both
+ *                         passes); 3: vector kernels reading the coefficients
+ *                         with scalar loads
  * Returns BCG_ERR_ARG for an unknown option. */
 enum { BCG_OPT_HOP_TR = 0, BCG_OPT_HOP_TPB = 1, BCG_OPT_HOP_PIPELINE = 2, BCG_OPT_PASS_CPT = 3,
        BCG_OPT_FUSE_GRAM = 4, BCG_OPT_HOP_KERNEL = 5, BCG_OPT_GRAM_KERNEL = 6, BCG_OPT_SMALL_THREADS = 7,

@@ -628,14 +628,14 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
                 {
                     Prof pr(ctx, BCG_K_PASS_A);
                     HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, ctx->partials, ctx->opt[BCG_OPT_PASS_CPT], bps64(ctx),
-                                          ctx->opt[BCG_OPT_PASS_KERNEL] != 2, s));
+                                          ctx->opt[BCG_OPT_PASS_KERNEL], s));
                 }
                 RETCK(reduce(ctx, ctx->partials, n_h, nullptr, 0, 0.0, N, M(ctx, M_H), halt));
             } else {
                 {
                     Prof pr(ctx, BCG_K_PASS_A);
                     HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, nullptr, ctx->opt[BCG_OPT_PASS_CPT], bps64(ctx),
-                                          ctx->opt[BCG_OPT_PASS_KERNEL] != 2, s));
+                                          ctx->opt[BCG_OPT_PASS_KERNEL], s));
                 }
                 RETCK(gram(ctx, ps, Q, Q, N, M(ctx, M_H), halt));
             }
@@ -647,7 +647,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
                 Prof pr(ctx, BCG_K_PASS_B);
                 HIPCK(launch_pass_b(ps, X, Q, P, Qn, Pn, M(ctx, M_BETAC), M(ctx, M_SINV), M(ctx, M_SH),
                                     N, Vh, st, fuse ? ctx->part_pp : nullptr, ctx->opt[BCG_OPT_PASS_CPT], bps64(ctx),
-                                    ctx->opt[BCG_OPT_PASS_KERNEL] != 2, s));
+                                    ctx->opt[BCG_OPT_PASS_KERNEL], s));
             }
             n_pp = fused_grid(Vh);
             c = 1 - c;

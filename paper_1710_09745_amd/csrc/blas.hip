@@ -528,10 +528,91 @@ static int pass_cpt(int N, int cpt_req) {
     return N < c ? (N == 1 ? 1 : (N == 2 ? 2 : c)) : c;
 }
 
+// Pass A on the vector ALUs with beta staged in LDS (blocks of 16 columns, as
+// k_pass_b_st), persistent over site blocks.  Pass A reads one coefficient matrix,
+// and its scalar-load version measured faster (32^3 x 64, N = 16 ... 64), so this
+// one is used only on request.
+template <typename S, int LB = std::is_same<S, F64>::value ? 2 : 4>
+__global__ void __launch_bounds__(256)
+k_pass_a_st(typename S::pair* __restrict__ Q, float* __restrict__ Qs, const typename S::pair* __restrict__ AP,
+            const float* __restrict__ APs, const double2* __restrict__ beta, int N, int Vh,
+            const int* __restrict__ halt, int bps) {
+    using R = typename S::real;
+    constexpr int CPT = 4;
+    extern __shared__ double2 cfs[];  // [N][16]
+    if (halt != nullptr && *halt) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nsb = (Vh + 63) / 64;
+    for (int jb = 0; jb < N; jb += 16) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < N * 16; e += 256) {
+            const int l = e >> 4, j = jb + (e & 15);
+            cfs[e] = j < N ? beta[l * MAXN + j] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        const int j0 = jb + wave * CPT;
+        if (j0 >= N) continue;
+        const int jl = wave * CPT;
+        for (int it = blockIdx.x; it < nsb; it += gridDim.x) {
+            int sb, tg_unused;
+            xcd_task(it, nsb, 1, bps, sb, tg_unused);
+            const int i0 = sb * 64 + lane;
+            const bool valid = i0 < Vh;
+            const int i = valid ? i0 : Vh - 1;
+            C2<R> acc2[CPT][3];
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc2[m][c] = C2<R>{0, 0};
+            for (int l0 = 0; l0 < N; l0 += LB) {
+                C2<R> a[LB][3];
+#pragma unroll
+                for (int u = 0; u < LB; ++u) load_group<S, 3>(AP, APs, Vh, l0 + u < N ? l0 + u : N - 1, i, a[u]);
+#pragma unroll
+                for (int u = 0; u < LB; ++u) {
+                    if (l0 + u < N) {
+#pragma unroll
+                        for (int m = 0; m < CPT; ++m) {
+                            const double2 bd = cfs[(l0 + u) * 16 + jl + m];
+                            const C2<R> b{(R)bd.x, (R)bd.y};
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) cmac(acc2[m][c], a[u][c], b);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                if (j0 + m < N && valid) {
+                    C2<R> q[3];
+                    load_group<S, 3>(Q, Qs, Vh, j0 + m, i, q);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        q[c].re -= acc2[m][c].re;
+                        q[c].im -= acc2[m][c].im;
+                    }
+                    store_group<S, 3, R>(Q, Qs, Vh, j0 + m, i, q);
+                }
+            }
+        }
+    }
+}
+
 template <typename S, int CPT, int NB, bool GR>
 static void pass_a_go(void* Q, const void* AP, const double2* beta, int N, int Vh, const int* halt,
-                      double2* partials, int bps, hipStream_t s) {
+                      double2* partials, int bps, bool staged, hipStream_t s) {
     using P = typename S::pair;
+    if constexpr (!GR) {
+        if (CPT == 4 && staged) {
+            const int nsb = (Vh + 63) / 64;
+            const int grid = nsb < 2048 ? nsb : 2048;
+            hipLaunchKernelGGL((k_pass_a_st<S>), dim3(grid), dim3(256), (size_t)N * 16 * sizeof(double2), s, (P*)Q,
+                               scale_of<S>(Q, N, 3, Vh), (const P*)AP, scale_of<S>(AP, N, 3, Vh), beta, N, Vh, halt,
+                               bps);
+            return;
+        }
+    }
     const int grid = GR ? fused_grid(Vh) : (Vh + 63) / 64;
     const size_t lds = GR ? FusedTile<S, NB>::bytes : 0;
     hipLaunchKernelGGL((k_pass_a<S, CPT, NB, GR>), dim3(grid), dim3(256), lds, s, (P*)Q, scale_of<S>(Q, N, 3, Vh),
@@ -540,26 +621,26 @@ static void pass_a_go(void* Q, const void* AP, const double2* beta, int N, int V
 
 template <typename S, int CPT>
 static void pass_a_nb(void* Q, const void* AP, const double2* beta, int N, int Vh, const int* halt,
-                      double2* partials, int bps, hipStream_t s) {
-    if (partials == nullptr) return pass_a_go<S, CPT, 1, false>(Q, AP, beta, N, Vh, halt, nullptr, bps, s);
+                      double2* partials, int bps, bool staged, hipStream_t s) {
+    if (partials == nullptr) return pass_a_go<S, CPT, 1, false>(Q, AP, beta, N, Vh, halt, nullptr, bps, staged, s);
     switch (pad_n(N)) {
-        case 1: return pass_a_go<S, CPT, 1, true>(Q, AP, beta, N, Vh, halt, partials, bps, s);
-        case 2: return pass_a_go<S, CPT, 2, true>(Q, AP, beta, N, Vh, halt, partials, bps, s);
-        case 4: return pass_a_go<S, CPT, 4, true>(Q, AP, beta, N, Vh, halt, partials, bps, s);
-        case 8: return pass_a_go<S, CPT, 8, true>(Q, AP, beta, N, Vh, halt, partials, bps, s);
-        case 16: return pass_a_go<S, CPT, 16, true>(Q, AP, beta, N, Vh, halt, partials, bps, s);
+        case 1: return pass_a_go<S, CPT, 1, true>(Q, AP, beta, N, Vh, halt, partials, bps, staged, s);
+        case 2: return pass_a_go<S, CPT, 2, true>(Q, AP, beta, N, Vh, halt, partials, bps, staged, s);
+        case 4: return pass_a_go<S, CPT, 4, true>(Q, AP, beta, N, Vh, halt, partials, bps, staged, s);
+        case 8: return pass_a_go<S, CPT, 8, true>(Q, AP, beta, N, Vh, halt, partials, bps, staged, s);
+        case 16: return pass_a_go<S, CPT, 16, true>(Q, AP, beta, N, Vh, halt, partials, bps, staged, s);
         default:
-            if constexpr (!std::is_same<S, F64>::value) return pass_a_go<S, CPT, 32, true>(Q, AP, beta, N, Vh, halt, partials, bps, s);
+            if constexpr (!std::is_same<S, F64>::value) return pass_a_go<S, CPT, 32, true>(Q, AP, beta, N, Vh, halt, partials, bps, staged, s);
     }
 }
 
 template <typename S>
 static void pass_a_t(void* Q, const void* AP, const double2* beta, int N, int Vh, const int* halt,
-                     double2* partials, int cpt_req, int bps, hipStream_t s) {
+                     double2* partials, int cpt_req, int bps, bool staged, hipStream_t s) {
     const int cpt = pass_cpt(N, cpt_req);
-    if (cpt == 1) pass_a_nb<S, 1>(Q, AP, beta, N, Vh, halt, partials, bps, s);
-    else if (cpt == 2) pass_a_nb<S, 2>(Q, AP, beta, N, Vh, halt, partials, bps, s);
-    else pass_a_nb<S, 4>(Q, AP, beta, N, Vh, halt, partials, bps, s);
+    if (cpt == 1) pass_a_nb<S, 1>(Q, AP, beta, N, Vh, halt, partials, bps, staged, s);
+    else if (cpt == 2) pass_a_nb<S, 2>(Q, AP, beta, N, Vh, halt, partials, bps, staged, s);
+    else pass_a_nb<S, 4>(Q, AP, beta, N, Vh, halt, partials, bps, staged, s);
 }
 
 // Pass A on the matrix cores (FP32 / FP64 storage, 16 < N <= 32), the same
@@ -632,9 +713,10 @@ k_pass_a_mfma(typename S::pair* __restrict__ Q, const typename S::pair* __restri
 }
 
 hipError_t launch_pass_a(Prec prec, void* Q, const void* AP, const double2* beta, int N, int Vh,
-                         const int* halt, double2* partials, int cpt, int bps, bool mfma, hipStream_t s) {
+                         const int* halt, double2* partials, int cpt, int bps, int kernel, hipStream_t s) {
     if (partials != nullptr && fused_tile_bytes(prec, N) == 0) return hipErrorInvalidValue;
-    if (mfma && partials == nullptr && N > 16 && N <= 32 && (prec == Prec::FP64 || prec == Prec::FP32)) {
+    if ((kernel == 0 || kernel == 1) && partials == nullptr && N > 16 && N <= 32 &&
+        (prec == Prec::FP64 || prec == Prec::FP32)) {
         const long groups = ((long)((Vh + 15) / 16) * 3 + 3) / 4;
         const dim3 grid((unsigned)(groups < 2048 ? groups : 2048));
         const size_t lds = (size_t)32 * 32 * sizeof(double2);
@@ -647,10 +729,10 @@ hipError_t launch_pass_a(Prec prec, void* Q, const void* AP, const double2* beta
         return hipGetLastError();
     }
     switch (prec) {
-        case Prec::FP64: pass_a_t<F64>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, s); break;
-        case Prec::FP32: pass_a_t<F32>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, s); break;
-        case Prec::FP16: pass_a_t<H16>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, s); break;
-        case Prec::BF16: pass_a_t<B16>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, s); break;
+        case Prec::FP64: pass_a_t<F64>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, kernel == 2, s); break;
+        case Prec::FP32: pass_a_t<F32>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, kernel == 2, s); break;
+        case Prec::FP16: pass_a_t<H16>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, kernel == 2, s); break;
+        case Prec::BF16: pass_a_t<B16>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, kernel == 2, s); break;
     }
     return hipGetLastError();
 }
@@ -793,11 +875,147 @@ k_pass_b(double2* __restrict__ X, const typename S::pair* __restrict__ Qt, const
     if (gram) gram_finish<NB>(acc, reinterpret_cast<C2<double>*>(lds_raw), partials + (long)blockIdx.x * NB * NB);
 }
 
+// Pass B on the vector ALUs with the coefficients in LDS.  The coefficient reads
+// of the kernel above are wave-uniform scalar loads, and a 64 x 64 FP64 matrix
+// does not stay in the scalar cache, so every column step waited on L2.  Here the
+// workgroup stages a block of 16 columns of beta C, S^{-1} and S^H ([3][N][16], at
+// most 48 KB) in LDS and then sweeps its share of the site blocks for those
+// columns (wave w takes columns 4w .. 4w+3 of the block); the coefficient reads are
+// LDS broadcasts.  Persistent grid: block jb is staged once per workgroup.
+template <typename S, int LB = std::is_same<S, F64>::value ? 2 : 4>
+__global__ void __launch_bounds__(256)
+k_pass_b_st(double2* __restrict__ X, const typename S::pair* __restrict__ Qt, const float* __restrict__ Qts,
+            const typename S::pair* __restrict__ P, const float* __restrict__ Ps,
+            typename S::pair* __restrict__ Qn, float* __restrict__ Qns, typename S::pair* __restrict__ Pn,
+            float* __restrict__ Pns, const double2* __restrict__ betaC, const double2* __restrict__ Sinv,
+            const double2* __restrict__ SH, int N, int Vh, const SolveState* __restrict__ stt, int bps) {
+    using R = typename S::real;
+    constexpr int CPT = 4;
+    extern __shared__ double2 cfs[];  // [3][N][16]
+    const int mode = stt->pb_mode;
+    if (mode == PB_SKIP) return;
+    const bool full = (mode == PB_FULL);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nsb = (Vh + 63) / 64;
+    for (int jb = 0; jb < N; jb += 16) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 3 * N * 16; e += 256) {
+            const int mat = e / (N * 16), rem = e - mat * N * 16;
+            const int l = rem >> 4, j = jb + (rem & 15);
+            const double2* M = mat == 0 ? betaC : (mat == 1 ? Sinv : SH);
+            cfs[e] = j < N ? M[l * MAXN + j] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        const int j0 = jb + wave * CPT;
+        if (j0 >= N) continue;
+        const int jl = wave * CPT;  // column of the staged block
+        const double2* cb = cfs;
+        const double2* ci = cfs + N * 16;
+        const double2* ch = cfs + 2 * N * 16;
+        for (int it = blockIdx.x; it < nsb; it += gridDim.x) {
+            int sb, tg_unused;
+            xcd_task(it, nsb, 1, bps, sb, tg_unused);
+            const int i0 = sb * 64 + lane;
+            const bool valid = i0 < Vh;
+            const int i = valid ? i0 : Vh - 1;
+            C2<double> xa[CPT][3];
+            C2<R> qa[CPT][3], pa[CPT][3];
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xa[m][c] = C2<double>{0.0, 0.0};
+                    qa[m][c] = C2<R>{0, 0};
+                    pa[m][c] = C2<R>{0, 0};
+                }
+            for (int l0 = 0; l0 < N; l0 += LB) {
+                const bool needq = full && l0 < j0 + CPT;
+                C2<R> p[LB][3], q[LB][3];
+#pragma unroll
+                for (int u = 0; u < LB; ++u) load_group<S, 3>(P, Ps, Vh, l0 + u < N ? l0 + u : N - 1, i, p[u]);
+                if (needq) {
+#pragma unroll
+                    for (int u = 0; u < LB; ++u) load_group<S, 3>(Qt, Qts, Vh, l0 + u < N ? l0 + u : N - 1, i, q[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < LB; ++u) {
+                    const int l = l0 + u;
+                    if (l >= N) break;
+#pragma unroll
+                    for (int m = 0; m < CPT; ++m) {
+                        const double2 bc = cb[l * 16 + jl + m];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            cmac(xa[m][c], C2<double>{(double)p[u][c].re, (double)p[u][c].im}, C2<double>{bc.x, bc.y});
+                    }
+                    if (full) {
+#pragma unroll
+                        for (int m = 0; m < CPT; ++m) {
+                            if (l >= j0 + m) {
+                                const double2 sh = ch[l * 16 + jl + m];
+                                const C2<R> b{(R)sh.x, (R)sh.y};
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) cmac(pa[m][c], p[u][c], b);
+                            }
+                        }
+                        if (needq) {
+#pragma unroll
+                            for (int m = 0; m < CPT; ++m) {
+                                if (l <= j0 + m) {
+                                    const double2 si = ci[l * 16 + jl + m];
+                                    const C2<R> b{(R)si.x, (R)si.y};
+#pragma unroll
+                                    for (int c = 0; c < 3; ++c) cmac(qa[m][c], q[u][c], b);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                if (j0 + m < N && valid) {
+                    double2 xv[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) xv[c] = X[((long)(j0 + m) * 3 + c) * Vh + i];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        xv[c].x += xa[m][c].re;
+                        xv[c].y += xa[m][c].im;
+                        X[((long)(j0 + m) * 3 + c) * Vh + i] = xv[c];
+                    }
+                    if (full) {
+                        store_group<S, 3, R>(Qn, Qns, Vh, j0 + m, i, qa[m]);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            pa[m][c].re += qa[m][c].re;
+                            pa[m][c].im += qa[m][c].im;
+                        }
+                        store_group<S, 3, R>(Pn, Pns, Vh, j0 + m, i, pa[m]);
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <typename S, int CPT, int NB, bool GR>
 static void pass_b_go(double2* X, const void* Qt, const void* P, void* Qn, void* Pn, const double2* betaC,
                       const double2* Sinv, const double2* SH, int N, int Vh, const SolveState* st,
-                      double2* partials, int bps, hipStream_t s) {
+                      double2* partials, int bps, bool staged, hipStream_t s) {
     using PP = typename S::pair;
+    if constexpr (!GR) {
+        if (CPT == 4 && staged) {
+            const int nsb = (Vh + 63) / 64;
+            const int grid = nsb < 2048 ? nsb : 2048;
+            hipLaunchKernelGGL((k_pass_b_st<S>), dim3(grid), dim3(256), (size_t)3 * N * 16 * sizeof(double2), s, X,
+                               (const PP*)Qt, scale_of<S>(Qt, N, 3, Vh), (const PP*)P, scale_of<S>(P, N, 3, Vh),
+                               (PP*)Qn, scale_of<S>(Qn, N, 3, Vh), (PP*)Pn, scale_of<S>(Pn, N, 3, Vh), betaC, Sinv,
+                               SH, N, Vh, st, bps);
+            return;
+        }
+    }
     const int grid = GR ? fused_grid(Vh) : (Vh + 63) / 64;
     const size_t lds = GR ? FusedTile<S, NB>::bytes : 0;
     hipLaunchKernelGGL((k_pass_b<S, CPT, NB, GR>), dim3(grid), dim3(256), lds, s, X, (const PP*)Qt,
@@ -809,8 +1027,8 @@ static void pass_b_go(double2* X, const void* Qt, const void* P, void* Qn, void*
 template <typename S, int CPT>
 static void pass_b_nb(double2* X, const void* Qt, const void* P, void* Qn, void* Pn, const double2* betaC,
                       const double2* Sinv, const double2* SH, int N, int Vh, const SolveState* st,
-                      double2* partials, int bps, hipStream_t s) {
-#define PBG(NBV, GRV) pass_b_go<S, CPT, NBV, GRV>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, bps, s)
+                      double2* partials, int bps, bool staged, hipStream_t s) {
+#define PBG(NBV, GRV) pass_b_go<S, CPT, NBV, GRV>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, bps, staged, s)
     if (partials == nullptr) return PBG(1, false);
     switch (pad_n(N)) {
         case 1: return PBG(1, true);
@@ -827,11 +1045,11 @@ static void pass_b_nb(double2* X, const void* Qt, const void* P, void* Qn, void*
 template <typename S>
 static void pass_b_t(double2* X, const void* Qt, const void* P, void* Qn, void* Pn, const double2* betaC,
                      const double2* Sinv, const double2* SH, int N, int Vh, const SolveState* st,
-                     double2* partials, int cpt_req, int bps, hipStream_t s) {
+                     double2* partials, int cpt_req, int bps, bool staged, hipStream_t s) {
     const int cpt = pass_cpt(N, cpt_req);
-    if (cpt == 1) pass_b_nb<S, 1>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, bps, s);
-    else if (cpt == 2) pass_b_nb<S, 2>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, bps, s);
-    else pass_b_nb<S, 4>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, bps, s);
+    if (cpt == 1) pass_b_nb<S, 1>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, bps, staged, s);
+    else if (cpt == 2) pass_b_nb<S, 2>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, bps, staged, s);
+    else pass_b_nb<S, 4>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, st, partials, bps, staged, s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -986,19 +1204,20 @@ static void pass_b_mfma_t(double2* X, const void* Qt, const void* P, void* Qn, v
 
 hipError_t launch_pass_b(Prec prec, double2* X, const void* Qt, const void* P, void* Qn, void* Pn,
                          const double2* betaC, const double2* Sinv, const double2* SH, int N,
-                         int Vh, const SolveState* state, double2* partials, int cpt, int bps, bool mfma,
+                         int Vh, const SolveState* state, double2* partials, int cpt, int bps, int kernel,
                          hipStream_t s) {
     if (partials != nullptr && fused_tile_bytes(prec, N) == 0) return hipErrorInvalidValue;
-    if (mfma && pass_b_mfma_ok(prec, N, partials != nullptr)) {
+    const bool staged = kernel != 3;
+    if ((kernel == 0 || kernel == 1) && pass_b_mfma_ok(prec, N, partials != nullptr)) {
         if (prec == Prec::FP64) pass_b_mfma_t<F64>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, s);
         else pass_b_mfma_t<F32>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, s);
         return hipGetLastError();
     }
     switch (prec) {
-        case Prec::FP64: pass_b_t<F64>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, s); break;
-        case Prec::FP32: pass_b_t<F32>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, s); break;
-        case Prec::FP16: pass_b_t<H16>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, s); break;
-        case Prec::BF16: pass_b_t<B16>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, s); break;
+        case Prec::FP64: pass_b_t<F64>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, staged, s); break;
+        case Prec::FP32: pass_b_t<F32>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, staged, s); break;
+        case Prec::FP16: pass_b_t<H16>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, staged, s); break;
+        case Prec::BF16: pass_b_t<B16>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, staged, s); break;
     }
     return hipGetLastError();
 }

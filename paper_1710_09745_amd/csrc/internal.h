@@ -81,12 +81,12 @@ int fused_grid(int Vh);
 // Q <- Q - AP beta    (beta: [64][64] FP64); partials != nullptr: also Qt^H Qt partials
 // bps: 64-site blocks per time slice (workgroup order, xcd_task), 0 for the identity order
 hipError_t launch_pass_a(Prec prec, void* Q, const void* AP, const double2* beta, int N, int Vh,
-                         const int* halt, double2* partials, int cpt, int bps, bool mfma, hipStream_t s);
+                         const int* halt, double2* partials, int cpt, int bps, int kernel, hipStream_t s);
 // X += P betaC; Qn <- Qt Sinv; Pn <- Qn + P S^H, as selected by state->pb_mode;
 // partials != nullptr: also Pn^H Pn partials
 hipError_t launch_pass_b(Prec prec, double2* X, const void* Qt, const void* P, void* Qn, void* Pn,
                          const double2* betaC, const double2* Sinv, const double2* SH, int N,
-                         int Vh, const SolveState* state, double2* partials, int cpt, int bps, bool mfma,
+                         int Vh, const SolveState* state, double2* partials, int cpt, int bps, int kernel,
                          hipStream_t s);
 // Y <- Z + X M  (Z may be NULL = 0; X, Z may alias Y); X in precision px, Y/Z in py
 hipError_t launch_bmul(Prec px, const void* X, Prec py, const void* Z, void* Y, const double2* M,

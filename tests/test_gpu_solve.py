@@ -321,24 +321,24 @@ def test_site_orders_match_oracle(order, dims):
         assert col_rel_err(X3.cpu().numpy(), Xo).max() <= tol_x
 
 
-@pytest.mark.parametrize("n", [17, 32, 40, 64])
+@pytest.mark.parametrize("n", [5, 16, 17, 32, 40, 64])
 def test_pass_kernels_match_oracle(n):
     """Matrix-core (FP64 MFMA, transposed column tiles, triangular K-steps skipped;
-    used for 16 < N <= 32) and vector-ALU passes A and B give the oracle's iterates,
-    FP64 and FP32 storage."""
+    used for 16 < N <= 32), LDS-staged vector and scalar-load vector passes A and B
+    give the oracle's iterates (FP64, FP32) and converged solves (FP32, FP16, BF16)."""
     dims = (6, 6, 6, 8)
     fat, lng, B = inputs(dims, True, n, 7300 + n)
     m = 0.15
     op = oracle.Operator(dims, fat, lng, m)
     Xo, _ = oracle.block_cg_rq(op.apply, B, 1e-14, max_iter=3)
     for prec, tol_x in (("fp64", 1e-10), ("fp32", 1e-4)):
-        for kernel in (1, 2):
+        for kernel in (1, 2, 3):
             ctx = context(dims, True, fat, lng, m, tol=1e-14, ru_delta=0.0, max_iter=3, prec=prec)
             ctx.set_option("pass_kernel", kernel)
             X3, _ = ctx.solve(to_dev(B), raise_on_error=False)
             assert col_rel_err(X3.cpu().numpy(), Xo).max() <= tol_x, f"{prec} pass_kernel={kernel}"
     for prec in ("fp32", "fp16", "bf16"):
-        for kernel in (1, 2):
+        for kernel in (1, 3):
             ctx = context(dims, True, fat, lng, m, tol=1e-8, prec=prec)
             ctx.set_option("pass_kernel", kernel)
             X, info = ctx.solve(to_dev(B))
