@@ -176,10 +176,13 @@ int bcg_link_force(bcg_ctx *ctx, const void *X, const void *Lam, int nrhs, void 
  *                         2: vector kernels with LDS-staged coefficients (both
  *                         passes); 3: vector kernels reading the coefficients
  *                         with scalar loads
+ *   BCG_OPT_GRAPH         1: the solver iterations run as replays of a captured
+ *                         HIP graph of two iterations; 0 (default), 2: eager
+ *                         launches (always eager while kernel profiling is on)
  * Returns BCG_ERR_ARG for an unknown option. */
 enum { BCG_OPT_HOP_TR = 0, BCG_OPT_HOP_TPB = 1, BCG_OPT_HOP_PIPELINE = 2, BCG_OPT_PASS_CPT = 3,
        BCG_OPT_FUSE_GRAM = 4, BCG_OPT_HOP_KERNEL = 5, BCG_OPT_GRAM_KERNEL = 6, BCG_OPT_SMALL_THREADS = 7,
-       BCG_OPT_SITE_ORDER = 8, BCG_OPT_PASS_KERNEL = 9, BCG_OPT_COUNT = 10 };
+       BCG_OPT_SITE_ORDER = 8, BCG_OPT_PASS_KERNEL = 9, BCG_OPT_GRAPH = 10, BCG_OPT_COUNT = 11 };
 int bcg_set_option(bcg_ctx *ctx, int option, int value);
 
 /* Per-kernel timing with HIP events on the context's stream.  mask: bit set of

@@ -77,6 +77,7 @@ struct bcg_ctx {
     double prof_ms[BCG_K_COUNT]{};
     // tuning options (bcg_set_option), 0 = default
     int opt[BCG_OPT_COUNT]{};
+    hipStream_t cap_stream = nullptr;  // graph capture of the iteration loop
 };
 
 namespace {
@@ -139,6 +140,18 @@ hipEvent_t prof_event(bcg_ctx* ctx) {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
+
+// two instantiated graphs (one per starting ping-pong buffer), destroyed with the solve
+struct GraphPair {
+    hipGraph_t g[2] = {nullptr, nullptr};
+    hipGraphExec_t x[2] = {nullptr, nullptr};
+    ~GraphPair() {
+        for (int i = 0; i < 2; ++i) {
+            if (x[i]) (void)hipGraphExecDestroy(x[i]);
+            if (g[i]) (void)hipGraphDestroy(g[i]);
+        }
+    }
+};
 
 struct Prof {
     bcg_ctx* ctx;
@@ -386,6 +399,7 @@ int bcg_destroy(bcg_ctx* ctx) {
     if (ctx->d_vec) (void)hipFree(ctx->d_vec);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     if (ctx->h_vec) (void)hipHostFree(ctx->h_vec);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return BCG_OK;
 }
@@ -598,6 +612,84 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
     bool finished = (status != BCG_OK) || (ctx->h_state->max_relres <= ctx->tol);
     bool need_final_check = true;   // cleared when a reliable update has confirmed convergence
 
+    // one iteration of Alg. 1 on the ping-pong buffers c (P, Q) -> 1 - c (P', Q')
+    auto iteration = [&](int c) -> int {
+        void *P = Pb[c], *Q = Qb[c], *Pn = Pb[1 - c], *Qn = Qb[1 - c];
+        if (fuse) {
+            RETCK(hop(ctx, ps, 1, P, T, nullptr, N, EPI_PLAIN_, halt, nullptr, ctx->part_tt));
+            RETCK(hop(ctx, ps, 0, T, AP, P, N, EPI_MASS_, halt));
+            RETCK(reduce(ctx, ctx->part_tt, n_tt, ctx->part_pp, n_pp, m2, N, M(ctx, M_G), halt));
+        } else {
+            RETCK(hop(ctx, ps, 1, P, T, nullptr, N, EPI_PLAIN_, halt));
+            RETCK(hop(ctx, ps, 0, T, AP, P, N, EPI_MASS_, halt));
+            RETCK(gram(ctx, ps, P, AP, N, M(ctx, M_G), halt));
+        }
+        {
+            Prof pr(ctx, BCG_K_SMALL);
+            HIPCK(launch_small1(M(ctx, M_G), M(ctx, M_C), M(ctx, M_BETA), M(ctx, M_BETAC), st, N, ctx->opt[BCG_OPT_SMALL_THREADS], s));
+        }
+        if (fuse) {
+            {
+                Prof pr(ctx, BCG_K_PASS_A);
+                HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, ctx->partials, ctx->opt[BCG_OPT_PASS_CPT], bps64(ctx),
+                                      ctx->opt[BCG_OPT_PASS_KERNEL], s));
+            }
+            RETCK(reduce(ctx, ctx->partials, n_h, nullptr, 0, 0.0, N, M(ctx, M_H), halt));
+        } else {
+            {
+                Prof pr(ctx, BCG_K_PASS_A);
+                HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, nullptr, ctx->opt[BCG_OPT_PASS_CPT], bps64(ctx),
+                                      ctx->opt[BCG_OPT_PASS_KERNEL], s));
+            }
+            RETCK(gram(ctx, ps, Q, Q, N, M(ctx, M_H), halt));
+        }
+        {
+            Prof pr(ctx, BCG_K_SMALL);
+            HIPCK(launch_small2(M(ctx, M_H), M(ctx, M_C), M(ctx, M_SINV), M(ctx, M_SH), st, N, ctx->opt[BCG_OPT_SMALL_THREADS], s));
+        }
+        {
+            Prof pr(ctx, BCG_K_PASS_B);
+            HIPCK(launch_pass_b(ps, X, Q, P, Qn, Pn, M(ctx, M_BETAC), M(ctx, M_SINV), M(ctx, M_SH),
+                                N, Vh, st, fuse ? ctx->part_pp : nullptr, ctx->opt[BCG_OPT_PASS_CPT], bps64(ctx),
+                                ctx->opt[BCG_OPT_PASS_KERNEL], s));
+        }
+        return BCG_OK;
+    };
+    // HIP graph of two iterations starting on buffers c0 (so a replay ends where it
+    // began), captured on a private stream and replayed on the solver stream; only
+    // once the P^H P partials come from pass B (n_pp = n_h), so the kernel arguments
+    // are the same on every replay.  A failed capture falls back to eager launches.
+    GraphPair gp;
+    bool use_graph = ctx->opt[BCG_OPT_GRAPH] == 1 && ctx->prof_mask == 0;
+    auto capture = [&](int c0) {
+        if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+            ctx->cap_stream = nullptr;
+            use_graph = false;
+            return;
+        }
+        hipStream_t keep = ctx->stream;
+        ctx->stream = s = ctx->cap_stream;
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            int rc = iteration(c0);
+            if (rc == BCG_OK) rc = iteration(1 - c0);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(s, &g);
+            if (e == hipSuccess && rc == BCG_OK && g) {
+                gp.g[c0] = g;
+                e = hipGraphInstantiate(&gp.x[c0], g, nullptr, nullptr, 0);
+                if (e != hipSuccess) gp.x[c0] = nullptr;
+            } else if (g) {
+                (void)hipGraphDestroy(g);
+            }
+            if (rc != BCG_OK) e = hipErrorUnknown;
+        }
+        ctx->stream = s = keep;
+        if (e != hipSuccess || !gp.x[c0]) {
+            use_graph = false;
+            (void)hipGetLastError();
+        }
+    };
     while (!finished) {
         const SolveState& hs = *ctx->h_state;
         // chunk size from the estimated iterations to the next event
@@ -609,47 +701,15 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
         if (chunk > ctx->max_iter - hs.iters) chunk = ctx->max_iter - hs.iters;
         if (chunk < 1) chunk = 1;
         int c = cur;
-        for (int k = 0; k < chunk; ++k) {
-            void *P = Pb[c], *Q = Qb[c], *Pn = Pb[1 - c], *Qn = Qb[1 - c];
-            if (fuse) {
-                RETCK(hop(ctx, ps, 1, P, T, nullptr, N, EPI_PLAIN_, halt, nullptr, ctx->part_tt));
-                RETCK(hop(ctx, ps, 0, T, AP, P, N, EPI_MASS_, halt));
-                RETCK(reduce(ctx, ctx->part_tt, n_tt, ctx->part_pp, n_pp, m2, N, M(ctx, M_G), halt));
-            } else {
-                RETCK(hop(ctx, ps, 1, P, T, nullptr, N, EPI_PLAIN_, halt));
-                RETCK(hop(ctx, ps, 0, T, AP, P, N, EPI_MASS_, halt));
-                RETCK(gram(ctx, ps, P, AP, N, M(ctx, M_G), halt));
-            }
-            {
-                Prof pr(ctx, BCG_K_SMALL);
-                HIPCK(launch_small1(M(ctx, M_G), M(ctx, M_C), M(ctx, M_BETA), M(ctx, M_BETAC), st, N, ctx->opt[BCG_OPT_SMALL_THREADS], s));
-            }
-            if (fuse) {
-                {
-                    Prof pr(ctx, BCG_K_PASS_A);
-                    HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, ctx->partials, ctx->opt[BCG_OPT_PASS_CPT], bps64(ctx),
-                                          ctx->opt[BCG_OPT_PASS_KERNEL], s));
-                }
-                RETCK(reduce(ctx, ctx->partials, n_h, nullptr, 0, 0.0, N, M(ctx, M_H), halt));
-            } else {
-                {
-                    Prof pr(ctx, BCG_K_PASS_A);
-                    HIPCK(launch_pass_a(ps, Q, AP, M(ctx, M_BETA), N, Vh, halt, nullptr, ctx->opt[BCG_OPT_PASS_CPT], bps64(ctx),
-                                          ctx->opt[BCG_OPT_PASS_KERNEL], s));
-                }
-                RETCK(gram(ctx, ps, Q, Q, N, M(ctx, M_H), halt));
-            }
-            {
-                Prof pr(ctx, BCG_K_SMALL);
-                HIPCK(launch_small2(M(ctx, M_H), M(ctx, M_C), M(ctx, M_SINV), M(ctx, M_SH), st, N, ctx->opt[BCG_OPT_SMALL_THREADS], s));
-            }
-            {
-                Prof pr(ctx, BCG_K_PASS_B);
-                HIPCK(launch_pass_b(ps, X, Q, P, Qn, Pn, M(ctx, M_BETAC), M(ctx, M_SINV), M(ctx, M_SH),
-                                    N, Vh, st, fuse ? ctx->part_pp : nullptr, ctx->opt[BCG_OPT_PASS_CPT], bps64(ctx),
-                                    ctx->opt[BCG_OPT_PASS_KERNEL], s));
-            }
-            n_pp = fused_grid(Vh);
+        int k = 0;
+        if (use_graph && chunk >= 2 && (!fuse || n_pp == n_h)) {
+            if (!gp.x[c]) capture(c);
+            if (use_graph)
+                for (; k + 2 <= chunk; k += 2) HIPCK(hipGraphLaunch(gp.x[c], s));
+        }
+        for (; k < chunk; ++k) {
+            RETCK(iteration(c));
+            n_pp = n_h;
             c = 1 - c;
         }
         RETCK(read_state(ctx));

@@ -32,10 +32,27 @@ __device__ __forceinline__ void gst(double2* p, Z2 v) { *p = make_double2(v.re, 
 // partners of the factorisations) for N <= 32
 __host__ __device__ constexpr bool small_has_cold(int N) { return N <= 32; }
 
+// e / N for 1 <= N <= 64 and 0 <= e < 65 N (the row of entry e of a row-major
+// matrix with N columns) from a float reciprocal: (e + 1/2) / N lies at least
+// 1/(2N) from an integer and the reciprocal and product roundings move it by under
+// 2e-5, so the truncation is the integer quotient (checked for every such N and e)
+__device__ __forceinline__ int row_of(int e, int N) {
+    return (int)(((float)e + 0.5f) * __builtin_amdgcn_rcpf((float)N));
+}
+// offset of entry e in a global [64][64] matrix
+__device__ __forceinline__ int gofs(int e, int N) {
+    const int i = row_of(e, N);
+    return i * MAXN + (e - i * N);
+}
+__device__ __forceinline__ bool strict_upper(int e, int N) {
+    const int i = row_of(e, N);
+    return e - i * N > i;
+}
+
 // A <- (M + M^H)/2 for the leading N x N block of a global [64][64] matrix
 __device__ void load_herm(Z2* A, const double2* M, int N) {
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
+        const int i = row_of(e, N), j = e - i * N;
         const Z2 a = gld(M + i * MAXN + j), b = gld(M + j * MAXN + i);
         A[e] = Z2{0.5 * (a.re + b.re), 0.5 * (a.im - b.im)};
     }
@@ -43,7 +60,7 @@ __device__ void load_herm(Z2* A, const double2* M, int N) {
 
 // leading N x N block of a global [64][64] matrix into LDS (ld = N)
 __device__ void load_mat(Z2* A, const double2* M, int N) {
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) A[e] = gld(M + (e / N) * MAXN + e % N);
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) A[e] = gld(M + gofs(e, N));
 }
 
 // In-place lower Cholesky A = L L^H (L with positive real diagonal, strict upper
@@ -66,7 +83,7 @@ __device__ bool chol_lower(Z2* A, int N, const double* diag) {
         const int m = N - k - 1;
         if (threadIdx.x == 0) A[k * N + k] = Z2{d * rs, 0.0};
         for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-            const int i = k + 1 + e / m, j = k + 1 + e % m;
+            const int q = row_of(e, m), i = k + 1 + q, j = k + 1 + (e - q * m);
             if (j <= i) {
                 const Z2 p = zmul(A[i * N + k], zconj(A[j * N + k]));
                 A[i * N + j].re -= p.re;
@@ -76,7 +93,7 @@ __device__ bool chol_lower(Z2* A, int N, const double* diag) {
         __syncthreads();
     }
     for (int e = threadIdx.x; e < N * N; e += blockDim.x)
-        if (e % N > e / N) A[e] = Z2{0.0, 0.0};
+        if (strict_upper(e, N)) A[e] = Z2{0.0, 0.0};
     __syncthreads();
     return true;
 }
@@ -85,7 +102,7 @@ __device__ bool chol_lower(Z2* A, int N, const double* diag) {
 // (two barriers per column, all updates of a column in parallel).
 __device__ void tri_inv_lower(const Z2* L, Z2* Zm, int N) {
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
+        const int i = row_of(e, N), j = e - i * N;
         Zm[e] = Z2{i == j ? 1.0 : 0.0, 0.0};
     }
     __syncthreads();
@@ -98,7 +115,7 @@ __device__ void tri_inv_lower(const Z2* L, Z2* Zm, int N) {
         __syncthreads();
         const int w = k + 1, m = N - k - 1;
         for (int e = threadIdx.x; e < m * w; e += blockDim.x) {
-            const int i = k + 1 + e / w, j = e % w;
+            const int q = row_of(e, w), i = k + 1 + q, j = e - q * w;
             const Z2 p = zmul(L[i * N + k], Zm[k * N + j]);
             Zm[i * N + j].re -= p.re;
             Zm[i * N + j].im -= p.im;
@@ -113,7 +130,7 @@ __device__ void tri_inv_lower(const Z2* L, Z2* Zm, int N) {
 // as chol_lower.
 __device__ bool chol_inv_lower(Z2* A, Z2* Zm, int N, const double* diag) {
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
+        const int i = row_of(e, N), j = e - i * N;
         Zm[e] = Z2{i == j ? 1.0 : 0.0, 0.0};
     }
     __syncthreads();
@@ -138,7 +155,7 @@ __device__ bool chol_inv_lower(Z2* A, Z2* Zm, int N, const double* diag) {
         const int m = N - k - 1;
         for (int e = threadIdx.x; e < m * m + m * (k + 1); e += blockDim.x) {
             if (e < m * m) {
-                const int i = k + 1 + e / m, j = k + 1 + e % m;
+                const int q = row_of(e, m), i = k + 1 + q, j = k + 1 + (e - q * m);
                 if (j <= i) {
                     const Z2 p = zmul(A[i * N + k], zconj(A[j * N + k]));
                     A[i * N + j].re -= p.re;
@@ -146,7 +163,7 @@ __device__ bool chol_inv_lower(Z2* A, Z2* Zm, int N, const double* diag) {
                 }
             } else {
                 const int f = e - m * m;
-                const int i = k + 1 + f / (k + 1), j = f % (k + 1);
+                const int q = row_of(f, k + 1), i = k + 1 + q, j = f - q * (k + 1);
                 const Z2 p = zmul(A[i * N + k], Zm[k * N + j]);
                 Zm[i * N + j].re -= p.re;
                 Zm[i * N + j].im -= p.im;
@@ -155,7 +172,7 @@ __device__ bool chol_inv_lower(Z2* A, Z2* Zm, int N, const double* diag) {
         __syncthreads();
     }
     for (int e = threadIdx.x; e < N * N; e += blockDim.x)
-        if (e % N > e / N) A[e] = Z2{0.0, 0.0};
+        if (strict_upper(e, N)) A[e] = Z2{0.0, 0.0};
     __syncthreads();
     return true;
 }
@@ -163,34 +180,30 @@ __device__ bool chol_inv_lower(Z2* A, Z2* Zm, int N, const double* diag) {
 // chol_inv_lower with two buffers per matrix: step k reads (X, ZX) and writes
 // (Y, ZY), then the roles swap, every thread forming the scaled column-k factors it
 // needs itself, so one barrier per step.  The same products as chol_inv_lower.
-// On return *L and *Zout point at the buffers holding L (lower, strict upper
-// zeroed) and L^{-1}; ok = false on a breakdown pivot (same rule as chol_lower).
+// All LDS operands of a step are read before the pivot's square root (the reads
+// do not depend on it), and the breakdown test follows the step's barrier (a
+// failed step's outputs are discarded).  On return *L and *Zout point at the
+// buffers holding L (lower, strict upper zeroed) and L^{-1}; ok = false on a
+// breakdown pivot (same rule as chol_lower).
 __device__ void chol_inv_lower_pp(Z2* X, Z2* Y, Z2* ZX, Z2* ZY, int N, const double* diag, bool& ok,
                                   Z2** L, Z2** Zout) {
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
+        const int i = row_of(e, N), j = e - i * N;
         ZX[e] = Z2{i == j ? 1.0 : 0.0, 0.0};
     }
     __syncthreads();
     for (int k = 0; k < N; ++k) {
         const double d = X[k * N + k].re;
-        const double floor_k = diag ? 1e-14 * diag[k] : 0.0;
-        if (!(d > floor_k) || !isfinite(d)) {
-            ok = false;
-            *L = X;
-            *Zout = ZX;
-            return;
-        }
         const double rs = 1.0 / sqrt(d);
         for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-            const int i = e / N, j = e % N;
+            const int i = row_of(e, N), j = e - i * N;
+            const Z2 xe = X[e], a = X[i * N + k], b = X[j * N + k], ze = ZX[e], zk = ZX[k * N + j];
             // L part (lower triangle only; the strict upper triangle is never read)
             if (j <= i) {
-                Z2 v = X[e];
+                Z2 v = xe;
                 if (j == k) {
                     v = (i == k) ? Z2{d * rs, 0.0} : Z2{v.re * rs, v.im * rs};
                 } else if (j > k) {
-                    const Z2 a = X[i * N + k], b = X[j * N + k];
                     const Z2 p = zmul(Z2{a.re * rs, a.im * rs}, zconj(Z2{b.re * rs, b.im * rs}));
                     v.re -= p.re;
                     v.im -= p.im;
@@ -199,11 +212,10 @@ __device__ void chol_inv_lower_pp(Z2* X, Z2* Y, Z2* ZX, Z2* ZY, int N, const dou
             }
             // Z part: row k scaled, rows below k updated with the scaled row k
             if (j <= k || j <= i) {
-                Z2 z = ZX[e];
+                Z2 z = ze;
                 if (i == k && j <= k) {
                     z = Z2{z.re * rs, z.im * rs};
                 } else if (i > k && j <= k) {
-                    const Z2 a = X[i * N + k], zk = ZX[k * N + j];
                     const Z2 p = zmul(Z2{a.re * rs, a.im * rs}, Z2{zk.re * rs, zk.im * rs});
                     z.re -= p.re;
                     z.im -= p.im;
@@ -212,6 +224,13 @@ __device__ void chol_inv_lower_pp(Z2* X, Z2* Y, Z2* ZX, Z2* ZY, int N, const dou
             }
         }
         __syncthreads();
+        const double floor_k = diag ? 1e-14 * diag[k] : 0.0;
+        if (!(d > floor_k) || !isfinite(d)) {
+            ok = false;
+            *L = X;
+            *Zout = ZX;
+            return;
+        }
         Z2* t = X;
         X = Y;
         Y = t;
@@ -220,7 +239,7 @@ __device__ void chol_inv_lower_pp(Z2* X, Z2* Y, Z2* ZX, Z2* ZY, int N, const dou
         ZY = t;
     }
     for (int e = threadIdx.x; e < N * N; e += blockDim.x)
-        if (e % N > e / N) X[e] = Z2{0.0, 0.0};
+        if (strict_upper(e, N)) X[e] = Z2{0.0, 0.0};
     __syncthreads();
     ok = true;
     *L = X;
@@ -243,7 +262,7 @@ __device__ bool gj_inverse_hpd(Z2* A, int N, Z2* rowk, Z2* colk) {
         }
         __syncthreads();
         for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-            const int i = e / N, j = e % N;
+            const int i = row_of(e, N), j = e - i * N;
             if (i == k) {
                 A[e] = rowk[j];
             } else {
@@ -259,30 +278,33 @@ __device__ bool gj_inverse_hpd(Z2* A, int N, Z2* rowk, Z2* colk) {
 
 // The same Gauss-Jordan elimination with two buffers: step k reads X and writes Y
 // (then the roles swap), every thread forming its own pivot-row and pivot-column
-// factors, so one barrier per step.  Identical arithmetic to gj_inverse_hpd.
+// factors, so one barrier per step.  Identical arithmetic to gj_inverse_hpd.  The
+// LDS operands of a step are read before the pivot's reciprocal and the pivot test
+// follows the step's barrier (a failed step's output is discarded).
 // Returns the buffer holding the inverse; ok = false on a non-positive pivot.
 __device__ Z2* gj_inverse_hpd_pp(Z2* X, Z2* Y, int N, bool& ok) {
     __syncthreads();
     for (int k = 0; k < N; ++k) {
         const double p = X[k * N + k].re;
-        if (!(p > 0.0) || !isfinite(p)) {
-            ok = false;
-            return X;
-        }
         const double pinv = 1.0 / p;
         for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-            const int i = e / N, j = e % N;
-            const Z2 xkj = (j == k) ? Z2{1.0, 0.0} : X[k * N + j];
+            const int i = row_of(e, N), j = e - i * N;
+            const Z2 xk = X[k * N + j], xe = X[e], xi = X[i * N + k];
+            const Z2 xkj = (j == k) ? Z2{1.0, 0.0} : xk;
             const Z2 rk{xkj.re * pinv, xkj.im * pinv};
             if (i == k) {
                 Y[e] = rk;
             } else {
-                const Z2 base = (j == k) ? Z2{0.0, 0.0} : X[e];
-                const Z2 q = zmul(X[i * N + k], rk);
+                const Z2 base = (j == k) ? Z2{0.0, 0.0} : xe;
+                const Z2 q = zmul(xi, rk);
                 Y[e] = Z2{base.re - q.re, base.im - q.im};
             }
         }
         __syncthreads();
+        if (!(p > 0.0) || !isfinite(p)) {
+            ok = false;
+            return X;
+        }
         Z2* t = X;
         X = Y;
         Y = t;
@@ -293,7 +315,9 @@ __device__ Z2* gj_inverse_hpd_pp(Z2* X, Z2* Y, int N, bool& ok) {
 
 // relres[i] = sqrt((C^H H C)_ii) / bnorm[i].  A group of G lanes (G = 16, 32 or
 // 64, the smallest power of two >= N) handles one column i, lane m forming
-// conj(C[m][i]) (H C)[m][i]; the group sums its lanes with shuffles.
+// conj(C[m][i]) (H C)[m][i]; the group sums its lanes with shuffles.  H must be
+// exactly Hermitian (as load_herm leaves it): lane m reads row n of H, so the
+// lanes of a group touch consecutive entries.
 __device__ void residual_norms(const Z2* H, const Z2* C, int N, const double* bnorm, double* rel) {
     const int G = N <= 16 ? 16 : (N <= 32 ? 32 : 64);
     const int groups = blockDim.x / G;
@@ -303,8 +327,8 @@ __device__ void residual_norms(const Z2* H, const Z2* C, int N, const double* bn
         double t = 0.0;
         if (i < N && m <= i) {   // C upper: C[m][i] = 0 for m > i, C[n][i] = 0 for n > i
             Z2 hc{0.0, 0.0};
-            for (int n = 0; n <= i; ++n) {
-                const Z2 q = zmul(H[m * N + n], C[n * N + i]);
+            for (int n = 0; n <= i; ++n) {   // H[m][n] = conj(H[n][m]) (exactly Hermitian), read by rows
+                const Z2 q = zmul(zconj(H[n * N + m]), C[n * N + i]);
                 hc.re += q.re;
                 hc.im += q.im;
             }
@@ -364,7 +388,7 @@ k_small_init(const double2* __restrict__ H, double2* __restrict__ C, double2* __
         return;
     }
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
+        const int i = row_of(e, N), j = e - i * N;
         gst(C + i * MAXN + j, (j >= i) ? zconj(A[j * N + i]) : Z2{0.0, 0.0});      // C = L^H
         gst(Cinv + i * MAXN + j, (j >= i) ? zconj(Zm[j * N + i]) : Z2{0.0, 0.0});  // C^{-1} = (L^{-1})^H
     }
@@ -422,7 +446,7 @@ k_small1(const double2* __restrict__ G, const double2* __restrict__ C, double2* 
     Z2 bv[4];   // N*N / blockDim <= 4 (the launcher guarantees it)
     int cnt = 0;
     for (int e = threadIdx.x; e < N * N; e += blockDim.x, ++cnt) {
-        const int i = e / N, j = e % N;
+        const int i = row_of(e, N), j = e - i * N;
         const Z2 a = Bi[e], b = Bi[j * N + i];
         bv[cnt] = Z2{0.5 * (a.re + b.re), 0.5 * (a.im - b.im)};
     }
@@ -430,11 +454,11 @@ k_small1(const double2* __restrict__ G, const double2* __restrict__ C, double2* 
     cnt = 0;
     for (int e = threadIdx.x; e < N * N; e += blockDim.x, ++cnt) {
         Bi[e] = bv[cnt];
-        gst(beta + (e / N) * MAXN + e % N, bv[cnt]);
+        gst(beta + gofs(e, N), bv[cnt]);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
+        const int i = row_of(e, N), j = e - i * N;
         Z2 s{0.0, 0.0};
         for (int m = 0; m <= j; ++m) {   // C upper triangular
             const Z2 p = zmul(Bi[i * N + m], Cm[m * N + j]);
@@ -505,7 +529,7 @@ k_small2(const double2* __restrict__ H, double2* __restrict__ C, double2* __rest
     Z2 cn[4];   // N*N / blockDim <= 4 (the launcher guarantees it)
     int cnt = 0;
     for (int e = threadIdx.x; e < N * N; e += blockDim.x, ++cnt) {
-        const int i = e / N, j = e % N;
+        const int i = row_of(e, N), j = e - i * N;
         Z2 s2{0.0, 0.0};
         for (int m = i; m <= j; ++m) {
             const Z2 c = cl ? Cold[m * N + j] : gld(C + m * MAXN + j);
@@ -517,10 +541,10 @@ k_small2(const double2* __restrict__ H, double2* __restrict__ C, double2* __rest
     }
     __syncthreads();
     cnt = 0;
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x, ++cnt) gst(C + (e / N) * MAXN + e % N, cn[cnt]);
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x, ++cnt) gst(C + gofs(e, N), cn[cnt]);
     // S^H = L; S^{-1} = (L^{-1})^H  (leading N x N blocks only)
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
+        const int i = row_of(e, N), j = e - i * N;
         gst(SH + i * MAXN + j, (j <= i) ? Lm[i * N + j] : Z2{0.0, 0.0});
         gst(Sinv + i * MAXN + j, (j >= i) ? zconj(Zm[j * N + i]) : Z2{0.0, 0.0});
     }
@@ -569,21 +593,21 @@ k_small_ru(const double2* __restrict__ H, double2* __restrict__ C, double2* __re
     }
     // C^ = L^H -> temporarily in SH; C^{-1} = (L^{-1})^H -> Chinv
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
+        const int i = row_of(e, N), j = e - i * N;
         gst(SH + i * MAXN + j, (j >= i) ? zconj(A[j * N + i]) : Z2{0.0, 0.0});
         gst(Chinv + i * MAXN + j, (j >= i) ? zconj(W[j * N + i]) : Z2{0.0, 0.0});
     }
     __syncthreads();
     // A <- C_k^H (lower), W <- (C_k^H)^{-1} = (C_k^{-1})^H
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
+        const int i = row_of(e, N), j = e - i * N;
         A[e] = (j <= i) ? zconj(gld(C + j * MAXN + i)) : Z2{0.0, 0.0};
     }
     __syncthreads();
     tri_inv_lower(A, W, N);
     // S^ = C^ C_k^{-1} (upper), C_k^{-1}[m][j] = conj(W[j][m])
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
+        const int i = row_of(e, N), j = e - i * N;
         Z2 s2{0.0, 0.0};
         for (int m = i; m <= j; ++m) {
             const Z2 p = zmul(gld(SH + i * MAXN + m), zconj(W[j * N + m]));
@@ -595,12 +619,12 @@ k_small_ru(const double2* __restrict__ H, double2* __restrict__ C, double2* __re
     __syncthreads();
     // C <- C^ ; then S^H
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int o = (e / N) * MAXN + e % N;
+        const int o = gofs(e, N);
         C[o] = SH[o];
     }
     __syncthreads();
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e % N;
+        const int i = row_of(e, N), j = e - i * N;
         gst(SH + i * MAXN + j, zconj(A[j * N + i]));
     }
     if (threadIdx.x == 0) {

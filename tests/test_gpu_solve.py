@@ -343,3 +343,27 @@ def test_pass_kernels_match_oracle(n):
             ctx.set_option("pass_kernel", kernel)
             X, info = ctx.solve(to_dev(B))
             assert true_rel_res(op, B, X.cpu().numpy()).max() <= 1e-8, f"{prec} pass_kernel={kernel}"
+
+
+@pytest.mark.parametrize("dims,n", [((6, 6, 6, 8), 4), ((8, 8, 8, 8), 16), ((6, 6, 6, 8), 33)])
+def test_graph_replays_match_eager(dims, n):
+    """The iteration loop replayed from a captured HIP graph (many replays per solve,
+    with eager work and host synchronisations between them) gives bit-identical
+    iterates to eager launches, on two solves in a row with different column counts,
+    and the solution still meets the oracle's residual bound."""
+    fat, lng, B = inputs(dims, True, n, 7400 + n)
+    m = 0.12
+    op = oracle.Operator(dims, fat, lng, m)
+    precs = (("fp64", 1e-10), ("fp32", 1e-8), ("bf16", 1e-8)) if n <= 16 else (("fp64", 1e-10), ("fp32", 1e-8))
+    for prec, tol in precs:
+        out = {}
+        for graph in (2, 1):
+            ctx = context(dims, True, fat, lng, m, tol=tol, prec=prec)
+            ctx.set_option("graph", graph)
+            X1, i1 = ctx.solve(to_dev(B))
+            X2, i2 = ctx.solve(to_dev(B[: max(1, n // 2)]))
+            out[graph] = (X1.cpu().numpy(), i1["iters"], X2.cpu().numpy(), i2["iters"])
+        e, g = out[2], out[1]
+        assert e[1] == g[1] and e[3] == g[3], f"{prec}: iterations eager {e[1]},{e[3]} graph {g[1]},{g[3]}"
+        assert np.array_equal(e[0], g[0]) and np.array_equal(e[2], g[2]), prec
+        assert true_rel_res(op, B, g[0]).max() <= tol
