@@ -63,41 +63,6 @@ __device__ void load_mat(Z2* A, const double2* M, int N) {
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) A[e] = gld(M + gofs(e, N));
 }
 
-// In-place lower Cholesky A = L L^H (L with positive real diagonal, strict upper
-// triangle zeroed), two barriers per column.  A pivot d_k that is not positive,
-// not finite, or (when diag != nullptr) not above 1e-14 of the column's own
-// original diagonal is a breakdown: returns false on every thread.  Every
-// thread reads the same pivot after a barrier, so the decision is uniform.
-__device__ bool chol_lower(Z2* A, int N, const double* diag) {
-    __syncthreads();
-    for (int k = 0; k < N; ++k) {
-        const double d = A[k * N + k].re;
-        const double floor_k = diag ? 1e-14 * diag[k] : 0.0;
-        if (!(d > floor_k) || !isfinite(d)) return false;
-        const double rs = 1.0 / sqrt(d);
-        for (int i = k + 1 + threadIdx.x; i < N; i += blockDim.x) {
-            const Z2 v = A[i * N + k];
-            A[i * N + k] = Z2{v.re * rs, v.im * rs};
-        }
-        __syncthreads();
-        const int m = N - k - 1;
-        if (threadIdx.x == 0) A[k * N + k] = Z2{d * rs, 0.0};
-        for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-            const int q = row_of(e, m), i = k + 1 + q, j = k + 1 + (e - q * m);
-            if (j <= i) {
-                const Z2 p = zmul(A[i * N + k], zconj(A[j * N + k]));
-                A[i * N + j].re -= p.re;
-                A[i * N + j].im -= p.im;
-            }
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x)
-        if (strict_upper(e, N)) A[e] = Z2{0.0, 0.0};
-    __syncthreads();
-    return true;
-}
-
 // Z = L^{-1} for lower-triangular L with real positive diagonal, column by column
 // (two barriers per column, all updates of a column in parallel).
 __device__ void tri_inv_lower(const Z2* L, Z2* Zm, int N) {
@@ -126,9 +91,14 @@ __device__ void tri_inv_lower(const Z2* L, Z2* Zm, int N) {
 
 // Cholesky A = L L^H (in place, lower) and Z = L^{-1} together: step k scales
 // column k of L and row k of Z (phase 1), then updates the trailing block of A and
-// the rows below k of Z (phase 2); two barriers per column.  Same breakdown rule
-// as chol_lower.
-__device__ bool chol_inv_lower(Z2* A, Z2* Zm, int N, const double* diag) {
+// the rows below k of Z (phase 2); two barriers per column.  Phase 1 also copies
+// the scaled column k into colk (LDS, N entries), which phase 2 reads: the lanes
+// then touch consecutive entries instead of a column of A.  L has a positive real
+// diagonal and a zeroed strict upper triangle.  A pivot d_k that is not positive,
+// not finite, or (when diag != nullptr) not above 1e-14 of the column's own
+// original diagonal is a breakdown: returns false on every thread (all threads
+// read the same pivot after a barrier, so the decision is uniform).
+__device__ bool chol_inv_lower(Z2* A, Z2* Zm, int N, const double* diag, Z2* colk) {
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
         const int i = row_of(e, N), j = e - i * N;
         Zm[e] = Z2{i == j ? 1.0 : 0.0, 0.0};
@@ -143,7 +113,9 @@ __device__ bool chol_inv_lower(Z2* A, Z2* Zm, int N, const double* diag) {
         for (int e = threadIdx.x; e < N; e += blockDim.x) {
             if (e > k) {
                 const Z2 v = A[e * N + k];
-                A[e * N + k] = Z2{v.re * rs, v.im * rs};
+                const Z2 l{v.re * rs, v.im * rs};
+                A[e * N + k] = l;
+                colk[e] = l;
             } else {
                 const Z2 v = Zm[k * N + e];
                 Zm[k * N + e] = Z2{v.re * rs, v.im * rs};
@@ -157,14 +129,14 @@ __device__ bool chol_inv_lower(Z2* A, Z2* Zm, int N, const double* diag) {
             if (e < m * m) {
                 const int q = row_of(e, m), i = k + 1 + q, j = k + 1 + (e - q * m);
                 if (j <= i) {
-                    const Z2 p = zmul(A[i * N + k], zconj(A[j * N + k]));
+                    const Z2 p = zmul(colk[i], zconj(colk[j]));
                     A[i * N + j].re -= p.re;
                     A[i * N + j].im -= p.im;
                 }
             } else {
                 const int f = e - m * m;
                 const int q = row_of(f, k + 1), i = k + 1 + q, j = f - q * (k + 1);
-                const Z2 p = zmul(A[i * N + k], Zm[k * N + j]);
+                const Z2 p = zmul(colk[i], Zm[k * N + j]);
                 Zm[i * N + j].re -= p.re;
                 Zm[i * N + j].im -= p.im;
             }
@@ -184,7 +156,7 @@ __device__ bool chol_inv_lower(Z2* A, Z2* Zm, int N, const double* diag) {
 // do not depend on it), and the breakdown test follows the step's barrier (a
 // failed step's outputs are discarded).  On return *L and *Zout point at the
 // buffers holding L (lower, strict upper zeroed) and L^{-1}; ok = false on a
-// breakdown pivot (same rule as chol_lower).
+// breakdown pivot (same rule as chol_inv_lower).
 __device__ void chol_inv_lower_pp(Z2* X, Z2* Y, Z2* ZX, Z2* ZY, int N, const double* diag, bool& ok,
                                   Z2** L, Z2** Zout) {
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
@@ -379,7 +351,8 @@ k_small_init(const double2* __restrict__ H, double2* __restrict__ C, double2* __
     load_herm(A, H, N);
     __syncthreads();
     for (int k = threadIdx.x; k < N; k += blockDim.x) diag[k] = A[k * N + k].re;
-    if (!chol_inv_lower(A, Zm, N, diag)) {
+    __shared__ Z2 colk[MAXN];
+    if (!chol_inv_lower(A, Zm, N, diag, colk)) {
         if (threadIdx.x == 0) {
             st->halt = 1;
             st->reason = HALT_BREAKDOWN_H;
@@ -512,7 +485,10 @@ k_small2(const double2* __restrict__ H, double2* __restrict__ C, double2* __rest
     Z2* Zm = W;
     bool ok;
     if (small_has_cold(N)) chol_inv_lower_pp(A, sm + 3 * N * N, W, sm + 4 * N * N, N, nullptr, ok, &Lm, &Zm);
-    else ok = chol_inv_lower(A, W, N, nullptr);
+    else {
+        __shared__ Z2 colk[MAXN];
+        ok = chol_inv_lower(A, W, N, nullptr, colk);
+    }
     if (!ok) {
         if (threadIdx.x == 0) {
             st->halt = 1;
@@ -583,7 +559,8 @@ k_small_ru(const double2* __restrict__ H, double2* __restrict__ C, double2* __re
     load_herm(A, H, N);
     __syncthreads();
     for (int k = threadIdx.x; k < N; k += blockDim.x) diag[k] = A[k * N + k].re;
-    if (!chol_inv_lower(A, W, N, diag)) {
+    __shared__ Z2 colk[MAXN];
+    if (!chol_inv_lower(A, W, N, diag, colk)) {
         if (threadIdx.x == 0) {
             st->halt = 1;
             st->reason = HALT_BREAKDOWN_H;
