@@ -59,9 +59,16 @@ def model_bytes_per_site(kernel, N, prec="fp64", nl=16, aliased_gram=None):
     return None
 
 
-def kernel_source_hash():
+# source file of each timed kernel; its counters also depend on the shared headers
+# and on the host code that picks its launch shape
+KERNEL_SOURCE = {"hop_oe": "hop.hip", "hop_eo": "hop.hip", "pass_a": "blas.hip", "pass_b": "blas.hip",
+                 "gram": "blas.hip"}
+
+
+def kernel_source_hash(kernel):
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith(".h")) + [KERNEL_SOURCE[kernel], "bcg_api.cpp"]
+    for f in files:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(f.encode())
             h.update(fh.read())
@@ -77,7 +84,7 @@ def load_traffic(kernel, workload_key, launch_bytes):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash(kernel):
         return None
     return float(d["hbm_bytes_per_launch"])
 
