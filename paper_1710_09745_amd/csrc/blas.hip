@@ -129,13 +129,28 @@ k_gram(const typename S::pair* __restrict__ A, const float* __restrict__ As_,
 // ---------------------------------------------------------------------------------------------
 typedef double dvec4 __attribute__((ext_vector_type(4)));
 
+// sites i and i + 1 (i even) of plane (col, c) of a 16-bit [N][3][Vh] field with its
+// per-(column, site) scales, decoded to float: one 8-byte load each for the packed
+// pairs and the two scales (the same values load_one_d gives)
+template <typename S>
+__device__ __forceinline__ void load_two(const typename S::pair* __restrict__ d, const float* __restrict__ sc,
+                                         long Vh, long col, int c, long i, C2<float>& v0, C2<float>& v1) {
+    const uint2 u = *reinterpret_cast<const uint2*>(d + (col * 3 + c) * Vh + i);
+    const float2 s = *reinterpret_cast<const float2*>(sc + col * Vh + i);
+    v0 = C2<float>{S::dec((unsigned short)(u.x & 0xffffu)) * s.x, S::dec((unsigned short)(u.x >> 16)) * s.x};
+    v1 = C2<float>{S::dec((unsigned short)(u.y & 0xffffu)) * s.y, S::dec((unsigned short)(u.y >> 16)) * s.y};
+}
+
 template <typename S, int NB, bool SAME> struct MfmaGram {
     using E = typename TileElem<S>::type;
     static constexpr int NT = NB / 16;
     static constexpr int NUP = NT * (NT + 1) / 2;
-    // rows per wave chunk: 16, or 8 or 4 when the per-wave tiles would exceed 64 KB per workgroup
+    // rows per wave chunk: 16, or 8 or 4 when the per-wave tiles would exceed 64 KB per
+    // workgroup; 16-bit storage takes 64 or 32 rows when they fit, so that the lanes of a
+    // column group (two sites each) cover 256 or 128 contiguous bytes per load
     static constexpr int TB = 4 * (NB + 1) * (int)sizeof(C2<E>) * (SAME ? 1 : 2);  // bytes per row
-    static constexpr int ROWS = (16 * TB <= 65536) ? 16 : ((8 * TB <= 65536) ? 8 : 4);
+    static constexpr int ROWS16 = (16 * TB <= 65536) ? 16 : ((8 * TB <= 65536) ? 8 : 4);
+    static constexpr int ROWS = !S::scaled ? ROWS16 : ((64 * TB <= 65536) ? 64 : ((32 * TB <= 65536) ? 32 : ROWS16));
     static constexpr int LD = NB + 1;
     static constexpr size_t tile_bytes = (size_t)4 * ROWS * LD * sizeof(C2<E>) * (SAME ? 1 : 2);
 };
@@ -147,7 +162,11 @@ k_gram_mfma(const typename S::pair* __restrict__ A, const float* __restrict__ As
             double2* __restrict__ partials, const int* __restrict__ halt) {
     using G = MfmaGram<S, NB, SAME>;
     using E = typename G::E;
-    constexpr int NT = G::NT, ROWS = G::ROWS, LD = G::LD, QG = 64 / ROWS;
+    // 16-bit storage: a lane fetches two consecutive sites per column with one 8-byte
+    // load of the packed pairs and one of the scales (the 4-byte loads of one site at a
+    // time made this Gram load-issue bound at twice the FP32 time for the same bytes)
+    constexpr int SPL = S::scaled ? 2 : 1;  // sites per lane in a fetch
+    constexpr int NT = G::NT, ROWS = G::ROWS, LD = G::LD, QG = 64 * SPL / ROWS;
     extern __shared__ unsigned char lds_raw[];
     C2<E>* ta = reinterpret_cast<C2<E>*>(lds_raw);
     C2<E>* tb = SAME ? ta : ta + 4 * ROWS * LD;
@@ -165,22 +184,43 @@ k_gram_mfma(const typename S::pair* __restrict__ A, const float* __restrict__ As
         acc_im[t] = dvec4{0.0, 0.0, 0.0, 0.0};
     }
     const int nchunks = ((Vh + ROWS - 1) / ROWS) * 3;
-    const int ls = lane % ROWS, lq = lane / ROWS;
+    const int ls = lane % (ROWS / SPL), lq = lane / (ROWS / SPL);
     // the next chunk is loaded into registers while the current one is multiplied
-    C2<E> ra[NB / QG], rb[SAME ? 1 : NB / QG];
+    C2<E> ra[SPL * NB / QG], rb[SAME ? 1 : SPL * NB / QG];
     auto fetch = [&](int ch) {
-        const int c = ch % 3, site = (ch / 3) * ROWS + ls;
-        const bool ok = site < Vh;
+        const int c = ch % 3, site = (ch / 3) * ROWS + SPL * ls;
 #pragma unroll
         for (int jj = 0; jj < NB / QG; ++jj) {
             const int j = jj * QG + lq;
-            C2<double> v{0.0, 0.0};
-            if (ok && j < N) v = load_one_d<S, 3>(A, As_, Vh, j, c, site);
-            ra[jj] = C2<E>{(E)v.re, (E)v.im};
-            if constexpr (!SAME) {
-                C2<double> u{0.0, 0.0};
-                if (ok && j < N) u = load_one_d<S, 3>(B, Bs_, Vh, j, c, site);
-                rb[jj] = C2<E>{(E)u.re, (E)u.im};
+            if constexpr (SPL == 1) {
+                const bool ok = site < Vh && j < N;
+                C2<double> v{0.0, 0.0};
+                if (ok) v = load_one_d<S, 3>(A, As_, Vh, j, c, site);
+                ra[jj] = C2<E>{(E)v.re, (E)v.im};
+                if constexpr (!SAME) {
+                    C2<double> u{0.0, 0.0};
+                    if (ok) u = load_one_d<S, 3>(B, Bs_, Vh, j, c, site);
+                    rb[jj] = C2<E>{(E)u.re, (E)u.im};
+                }
+            } else {
+                C2<E> v0{0.0f, 0.0f}, v1{0.0f, 0.0f}, u0{0.0f, 0.0f}, u1{0.0f, 0.0f};
+                if (j < N && site + 1 < Vh) {  // site is even and Vh a multiple of 8: aligned
+                    load_two<S>(A, As_, Vh, j, c, site, v0, v1);
+                    if constexpr (!SAME) load_two<S>(B, Bs_, Vh, j, c, site, u0, u1);
+                } else if (j < N && site < Vh) {
+                    const C2<double> a = load_one_d<S, 3>(A, As_, Vh, j, c, site);
+                    v0 = C2<E>{(E)a.re, (E)a.im};
+                    if constexpr (!SAME) {
+                        const C2<double> b = load_one_d<S, 3>(B, Bs_, Vh, j, c, site);
+                        u0 = C2<E>{(E)b.re, (E)b.im};
+                    }
+                }
+                ra[2 * jj] = v0;
+                ra[2 * jj + 1] = v1;
+                if constexpr (!SAME) {
+                    rb[2 * jj] = u0;
+                    rb[2 * jj + 1] = u1;
+                }
             }
         }
     };
@@ -190,10 +230,12 @@ k_gram_mfma(const typename S::pair* __restrict__ A, const float* __restrict__ As
     for (; ch < nchunks; ch += stride) {
         // stage ROWS x NB: lane (ls, lq) holds columns lq, lq + QG, ...
 #pragma unroll
-        for (int jj = 0; jj < NB / QG; ++jj) {
-            wa[ls * LD + jj * QG + lq] = ra[jj];
-            if constexpr (!SAME) wb[ls * LD + jj * QG + lq] = rb[jj];
-        }
+        for (int jj = 0; jj < NB / QG; ++jj)
+#pragma unroll
+            for (int q = 0; q < SPL; ++q) {
+                wa[(SPL * ls + q) * LD + jj * QG + lq] = ra[SPL * jj + q];
+                if constexpr (!SAME) wb[(SPL * ls + q) * LD + jj * QG + lq] = rb[SPL * jj + q];
+            }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
