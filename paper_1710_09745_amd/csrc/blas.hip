@@ -395,15 +395,16 @@ hipError_t launch_gram(Prec prec, const void* A, const void* B, int N, int Vh, d
 int gram_parts(int N, int Vh, bool mfma) { return gram_nparts(Vh, pad_n(N), mfma); }
 
 // out[i*64 + j] = sum_b pa[b][e] + alpha * sum_b pb[b][e], e = i*NB + j, in a fixed
-// order: 8 entries per workgroup, 32 lanes per entry each summing every 32nd
-// partial (16 independent loads in flight per lane), then the 32 lane totals.
+// order: 256 / LPE entries per workgroup, LPE lanes per entry each summing every
+// LPE-th partial (16 independent loads in flight per lane), then the LPE lane totals.
+template <int LPE>
 __device__ __forceinline__ void partial_sum(const double2* __restrict__ part, int P, int NN, int e,
                                             int lane, double& sr, double& si) {
-    for (int p0 = lane; p0 < P; p0 += 32 * 16) {
+    for (int p0 = lane; p0 < P; p0 += LPE * 16) {
         double2 v[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            const int p = p0 + 32 * u;
+            const int p = p0 + LPE * u;
             v[u] = p < P ? part[(long)p * NN + e] : make_double2(0.0, 0.0);
         }
 #pragma unroll
@@ -414,25 +415,27 @@ __device__ __forceinline__ void partial_sum(const double2* __restrict__ part, in
     }
 }
 
+template <int LPE>
 __global__ void __launch_bounds__(256)
 k_gram_reduce(const double2* __restrict__ pa, int na, const double2* __restrict__ pb, int nb,
               double alpha, int NB, int N, double2* __restrict__ out, const int* __restrict__ halt) {
+    constexpr int EPW = 256 / LPE;  // entries per workgroup
     if (halt != nullptr && *halt) return;
-    __shared__ double2 red[2][8][33];
-    const int ent = threadIdx.x >> 5, lane = threadIdx.x & 31;
-    const int e = blockIdx.x * 8 + ent;
+    __shared__ double2 red[2][EPW][LPE + 1];
+    const int ent = threadIdx.x / LPE, lane = threadIdx.x % LPE;
+    const int e = blockIdx.x * EPW + ent;
     const int NN = NB * NB;
     double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
     if (e < NN) {
-        partial_sum(pa, na, NN, e, lane, ar, ai);
-        if (pb != nullptr) partial_sum(pb, nb, NN, e, lane, br, bi);
+        partial_sum<LPE>(pa, na, NN, e, lane, ar, ai);
+        if (pb != nullptr) partial_sum<LPE>(pb, nb, NN, e, lane, br, bi);
     }
     red[0][ent][lane] = make_double2(ar, ai);
     red[1][ent][lane] = make_double2(br, bi);
     __syncthreads();
     if (lane == 0 && e < NN) {
         double tr = 0.0, ti = 0.0, ur = 0.0, ui = 0.0;
-        for (int g = 0; g < 32; ++g) {
+        for (int g = 0; g < LPE; ++g) {
             tr += red[0][ent][g].x;
             ti += red[0][ent][g].y;
             ur += red[1][ent][g].x;
@@ -443,11 +446,15 @@ k_gram_reduce(const double2* __restrict__ pa, int na, const double2* __restrict_
     }
 }
 
+constexpr int REDUCE_LPE = 32;
+
 hipError_t launch_gram_reduce(const double2* pa, int na, const double2* pb, int nb, double alpha, int N,
                               double2* out, const int* halt, hipStream_t s) {
     const int NBv = pad_n(N);
-    const int grid = (NBv * NBv + 7) / 8;
-    hipLaunchKernelGGL(k_gram_reduce, dim3(grid), dim3(256), 0, s, pa, na, pb, nb, alpha, NBv, N, out, halt);
+    constexpr int EPW = 256 / REDUCE_LPE;
+    const int grid = (NBv * NBv + EPW - 1) / EPW;
+    hipLaunchKernelGGL(k_gram_reduce<REDUCE_LPE>, dim3(grid), dim3(256), 0, s, pa, na, pb, nb, alpha, NBv, N, out,
+                       halt);
     return hipGetLastError();
 }
 
