@@ -141,11 +141,14 @@ hipEvent_t prof_event(bcg_ctx* ctx) {
     return e;
 }
 
-// two instantiated graphs (one per starting ping-pong buffer), destroyed with the solve
+// two instantiated graphs (one per starting ping-pong buffer), destroyed with the
+// solve once the stream they were launched on has drained
 struct GraphPair {
     hipGraph_t g[2] = {nullptr, nullptr};
     hipGraphExec_t x[2] = {nullptr, nullptr};
+    hipStream_t launched_on = nullptr;
     ~GraphPair() {
+        if (x[0] || x[1]) (void)hipStreamSynchronize(launched_on);
         for (int i = 0; i < 2; ++i) {
             if (x[i]) (void)hipGraphExecDestroy(x[i]);
             if (g[i]) (void)hipGraphDestroy(g[i]);
@@ -660,6 +663,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
     // once the P^H P partials come from pass B (n_pp = n_h), so the kernel arguments
     // are the same on every replay.  A failed capture falls back to eager launches.
     GraphPair gp;
+    gp.launched_on = s;
     bool use_graph = ctx->opt[BCG_OPT_GRAPH] == 1 && ctx->prof_mask == 0;
     auto capture = [&](int c0) {
         if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
