@@ -40,8 +40,8 @@ CSRC = os.path.join(ROOT, "paper_1710_09745_amd", "csrc")
 #   gram   : read both block vectors (6 N), or one when they alias (3 N)
 #   pass_a : read Q, AP, write Q                             (9 N components)
 #   pass_b : read Qt, P, write Q, P (12 N) + read and write the FP64 X (6 N x 16 B)
-VC = {"fp64": 16.0, "fp32": 8.0, "fp16": 4.0 + 4.0 / 3.0, "bf16": 4.0 + 4.0 / 3.0}
-LM = {"fp64": 144.0, "fp32": 72.0, "fp16": 40.0, "bf16": 40.0}
+VC = {"fp64": 16.0, "fp32": 8.0, "fp16": 4.0 + 4.0 / 3.0, "bf16": 4.0 + 4.0 / 3.0, "fix16": 4.0 + 4.0 / 3.0}
+LM = {"fp64": 144.0, "fp32": 72.0, "fp16": 40.0, "bf16": 40.0, "fix16": 40.0}
 
 
 def model_bytes_per_site(kernel, N, prec="fp64", nl=16, aliased_gram=None):
@@ -101,7 +101,7 @@ def main():
                     help="config2: 16^4, N=16, FP64 (default); config3: 32^3x64, FP32 + FP64 "
                          "reliable updates, tol 1e-8, N from --nrhs")
     ap.add_argument("--nrhs", type=int, default=16)
-    ap.add_argument("--prec", default=None, help="storage precision override (fp64/fp32/fp16/bf16)")
+    ap.add_argument("--prec", default=None, help="storage precision override (fp64/fp32/fp16/bf16/fix16)")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--sweep", default=None,
                     help="comma-separated N list: per-kernel GB/s of the 32^3x64 block iteration vs N "
@@ -241,7 +241,8 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32+f64", "fp16": "f16+f64", "bf16": "bf16+f64"}[prec],
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "fp16": "f16+f64", "bf16": "bf16+f64",
+                  "fix16": "i16+f32+f64"}[prec],
         "data": "synthetic",
         "config": {"workload": workload, "lattice": list(dims), "nrhs": N, "mass": m,
                    "tol": tol, "storage": prec, "parallelism": "single GPU"},

@@ -73,7 +73,9 @@ typedef enum {
     BCG_PREC_FP64 = 0,
     BCG_PREC_FP32 = 1,
     BCG_PREC_FP16 = 2,           /* FP16 components with one FP32 scale per site and column */
-    BCG_PREC_BF16 = 3            /* BF16 components with one FP32 scale per site and column */
+    BCG_PREC_BF16 = 3,           /* BF16 components with one FP32 scale per site and column */
+    BCG_PREC_FIX16 = 4           /* 16-bit fixed-point components (q / 32767 of the largest
+                                    component of the site and column, kept as an FP32 scale) */
 } bcg_prec;
 
 #define BCG_MAX_RHS 64           /* N <= 64 (Sec. 6: small N x N matrices) */

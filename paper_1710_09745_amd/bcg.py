@@ -27,7 +27,7 @@ STATUS_NAMES = {OK: "ok", ERR_ARG: "bad argument", ERR_HIP: "HIP error", ERR_NOM
                 ERR_NOT_CONVERGED: "not converged", ERR_BREAKDOWN: "breakdown",
                 ERR_STATE: "bad state"}
 
-PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
+PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "fix16": 4}
 OPTIONS = {"hop_tr": 0, "hop_tpb": 1, "hop_pipeline": 2, "pass_cpt": 3, "fuse_gram": 4, "hop_kernel": 5, "gram_kernel": 6,
            "small_threads": 7, "site_order": 8,
            "pass_kernel": 9, "graph": 10}

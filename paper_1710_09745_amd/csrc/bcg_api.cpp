@@ -457,7 +457,7 @@ int bcg_set_solver(bcg_ctx* ctx, double tol, int max_iter, int sloppy_prec, doub
     if (!ctx) return BCG_ERR_ARG;
     if (!(tol > 0.0) || !(tol < 1.0)) return fail(ctx, BCG_ERR_ARG, "tol must be in (0, 1)");
     if (max_iter < 1) return fail(ctx, BCG_ERR_ARG, "max_iter must be >= 1");
-    if (sloppy_prec < 0 || sloppy_prec > 3) return fail(ctx, BCG_ERR_ARG, "unknown precision");
+    if (sloppy_prec < 0 || sloppy_prec > 4) return fail(ctx, BCG_ERR_ARG, "unknown precision");
     if (!(ru_delta >= 0.0) || !(ru_delta < 1.0)) return fail(ctx, BCG_ERR_ARG, "ru_delta must be in [0, 1)");
     ctx->tol = tol;
     ctx->max_iter = max_iter;

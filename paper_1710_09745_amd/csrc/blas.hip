@@ -388,6 +388,7 @@ hipError_t launch_gram(Prec prec, const void* A, const void* B, int N, int Vh, d
         case Prec::FP32: gram_t<F32>(A, B, N, Vh, partials, halt, s, nb, mfma); break;
         case Prec::FP16: gram_t<H16>(A, B, N, Vh, partials, halt, s, nb, mfma); break;
         case Prec::BF16: gram_t<B16>(A, B, N, Vh, partials, halt, s, nb, mfma); break;
+        case Prec::FX16: gram_t<X16>(A, B, N, Vh, partials, halt, s, nb, mfma); break;
     }
     return hipGetLastError();
 }
@@ -782,6 +783,7 @@ hipError_t launch_pass_a(Prec prec, void* Q, const void* AP, const double2* beta
         case Prec::FP32: pass_a_t<F32>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, kernel == 2, s); break;
         case Prec::FP16: pass_a_t<H16>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, kernel == 2, s); break;
         case Prec::BF16: pass_a_t<B16>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, kernel == 2, s); break;
+        case Prec::FX16: pass_a_t<X16>(Q, AP, beta, N, Vh, halt, partials, cpt, bps, kernel == 2, s); break;
     }
     return hipGetLastError();
 }
@@ -1267,6 +1269,7 @@ hipError_t launch_pass_b(Prec prec, double2* X, const void* Qt, const void* P, v
         case Prec::FP32: pass_b_t<F32>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, staged, s); break;
         case Prec::FP16: pass_b_t<H16>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, staged, s); break;
         case Prec::BF16: pass_b_t<B16>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, staged, s); break;
+        case Prec::FX16: pass_b_t<X16>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, partials, cpt, bps, staged, s); break;
     }
     return hipGetLastError();
 }
@@ -1340,6 +1343,7 @@ static hipError_t bmul_y(Prec py, const void* X, const void* Z, void* Y, const d
         case Prec::FP32: bmul_t<SX, F32>(X, Z, Y, M, N, Vh, skip, s); break;
         case Prec::FP16: bmul_t<SX, H16>(X, Z, Y, M, N, Vh, skip, s); break;
         case Prec::BF16: bmul_t<SX, B16>(X, Z, Y, M, N, Vh, skip, s); break;
+        case Prec::FX16: bmul_t<SX, X16>(X, Z, Y, M, N, Vh, skip, s); break;
     }
     return hipGetLastError();
 }
@@ -1351,6 +1355,7 @@ hipError_t launch_bmul(Prec px, const void* X, Prec py, const void* Z, void* Y, 
         case Prec::FP32: return bmul_y<F32>(py, X, Z, Y, M, N, Vh, skip, s);
         case Prec::FP16: return bmul_y<H16>(py, X, Z, Y, M, N, Vh, skip, s);
         case Prec::BF16: return bmul_y<B16>(py, X, Z, Y, M, N, Vh, skip, s);
+        case Prec::FX16: return bmul_y<X16>(py, X, Z, Y, M, N, Vh, skip, s);
     }
     return hipErrorInvalidValue;
 }

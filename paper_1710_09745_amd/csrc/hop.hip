@@ -412,6 +412,7 @@ hipError_t links_from64(Prec pd, const void* W64, void* Wd, int nl, long Vh, hip
         case Prec::FP32: hipLaunchKernelGGL((k_group_from64<F32, 9>), grid, dim3(256), 0, s, (const double2*)W64, (float2*)Wd, sc, cols, Vh); break;
         case Prec::FP16: hipLaunchKernelGGL((k_group_from64<H16, 9>), grid, dim3(256), 0, s, (const double2*)W64, (unsigned int*)Wd, sc, cols, Vh); break;
         case Prec::BF16: hipLaunchKernelGGL((k_group_from64<B16, 9>), grid, dim3(256), 0, s, (const double2*)W64, (unsigned int*)Wd, sc, cols, Vh); break;
+        case Prec::FX16: hipLaunchKernelGGL((k_group_from64<X16, 9>), grid, dim3(256), 0, s, (const double2*)W64, (unsigned int*)Wd, sc, cols, Vh); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -596,6 +597,7 @@ hipError_t launch_hop(Prec prec, int nl, const void* W, const void* in, void* ou
         case Prec::FP32: launch_hop_s<F32>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s); break;
         case Prec::FP16: launch_hop_s<H16>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s); break;
         case Prec::BF16: launch_hop_s<B16>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s); break;
+        case Prec::FX16: launch_hop_s<X16>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s); break;
     }
     return hipGetLastError();
 }

@@ -7,7 +7,7 @@
 
 namespace bcg {
 
-enum class Prec { FP64 = 0, FP32 = 1, FP16 = 2, BF16 = 3 };
+enum class Prec { FP64 = 0, FP32 = 1, FP16 = 2, BF16 = 3, FX16 = 4 };
 
 constexpr int MAXN = 64;          // largest block size; N x N matrices use leading dimension 64
 constexpr int GRAM_BLOCKS = 512;  // workgroups of a Gram reduction (= rows of its partials)
@@ -31,7 +31,7 @@ inline int pd_bytes(Prec p) {
 }
 inline size_t store_bytes(Prec p, long cols, int K, long Vh) {
     size_t b = (size_t)pd_bytes(p) * cols * K * Vh;
-    if (p == Prec::FP16 || p == Prec::BF16) b += (size_t)4 * cols * Vh;
+    if (p == Prec::FP16 || p == Prec::BF16 || p == Prec::FX16) b += (size_t)4 * cols * Vh;
     return b;
 }
 

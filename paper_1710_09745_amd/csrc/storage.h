@@ -4,6 +4,7 @@
 //   F32 : complex float pairs                     ( 8 bytes per complex)
 //   H16 : FP16 pairs scaled by one FP32 number per (column, site)
 //   B16 : BF16 pairs scaled by one FP32 number per (column, site)
+//   X16 : 16-bit fixed-point pairs (q / 32767) scaled the same way
 //
 // A group of K complex numbers that share a scale is one (column, site) entry:
 // the 3 colour components of a vector, or the 9 entries of a folded link matrix.
@@ -53,6 +54,18 @@ struct B16 {
     static __device__ __forceinline__ float dec(unsigned short u) {
         return __builtin_bit_cast(float, (unsigned int)u << 16);
     }
+};
+
+struct X16 {
+    using real = float;
+    using pair = unsigned int;
+    static constexpr bool scaled = true;
+    static constexpr int bytes = 4;
+    // x in [-1, 1] (the group is divided by its largest component): q = rint(32767 x)
+    static __device__ __forceinline__ unsigned short enc(float x) {
+        return (unsigned short)(short)__float2int_rn(x * 32767.0f);
+    }
+    static __device__ __forceinline__ float dec(unsigned short u) { return (float)(short)u * (1.0f / 32767.0f); }
 };
 
 // Buffer-resource loads.  A resource is made from a wave-uniform base address

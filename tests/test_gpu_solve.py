@@ -186,10 +186,11 @@ def test_config2_full_size_solve_and_cg():
     assert resc.max() <= c["tol"]
 
 
-@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("prec", ["fp16", "bf16", "fix16"])
 def test_mixed_16bit_reaches_tolerance(prec):
-    """16-bit storage with one FP32 scale per site and column (vectors) or per
-    folded link matrix, FP32 arithmetic, FP64 Gram / CholQR / reliable updates."""
+    """16-bit storage (FP16, BF16 or 16-bit fixed point) with one FP32 scale per site
+    and column (vectors) or per folded link matrix, FP32 arithmetic, FP64 Gram /
+    CholQR / reliable updates."""
     dims = (8, 8, 8, 8)
     fat, lng, B = inputs(dims, True, 8, 6600)
     m = 0.1
@@ -206,7 +207,7 @@ def test_mixed_16bit_reaches_tolerance(prec):
     assert i16["reliable_updates"] >= 1
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16", "fix16"])
 def test_sloppy_iterates_track_fp64(prec):
     """The first iterations in reduced storage stay close to the FP64 iterates
     (error of the order of the storage precision times the small growth of a
@@ -214,7 +215,8 @@ def test_sloppy_iterates_track_fp64(prec):
     dims = (6, 6, 6, 6)
     fat, lng, B = inputs(dims, True, 4, 6700)
     m = 0.2
-    eps = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}[prec]
+    # fix16: half a step of q / 32767 relative to the largest component of the group
+    eps = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8, "fix16": 2.0 ** -16}[prec]
     c = context(dims, True, fat, lng, m, tol=1e-14, prec=prec, ru_delta=0.0, max_iter=3)
     Xs, _ = c.solve(to_dev(B), raise_on_error=False)
     op = oracle.Operator(dims, fat, lng, m)
@@ -337,7 +339,7 @@ def test_pass_kernels_match_oracle(n):
             ctx.set_option("pass_kernel", kernel)
             X3, _ = ctx.solve(to_dev(B), raise_on_error=False)
             assert col_rel_err(X3.cpu().numpy(), Xo).max() <= tol_x, f"{prec} pass_kernel={kernel}"
-    for prec in ("fp32", "fp16", "bf16"):
+    for prec in ("fp32", "fp16", "bf16", "fix16"):
         for kernel in (1, 3):
             ctx = context(dims, True, fat, lng, m, tol=1e-8, prec=prec)
             ctx.set_option("pass_kernel", kernel)
