@@ -248,38 +248,59 @@ __device__ bool gj_inverse_hpd(Z2* A, int N, Z2* rowk, Z2* colk) {
     return true;
 }
 
-// The same Gauss-Jordan elimination with two buffers: step k reads X and writes Y
-// (then the roles swap), every thread forming its own pivot-row and pivot-column
-// factors, so one barrier per step.  Identical arithmetic to gj_inverse_hpd.  The
-// LDS operands of a step are read before the pivot's reciprocal and the pivot test
-// follows the step's barrier (a failed step's output is discarded).
-// Returns the buffer holding the inverse; ok = false on a non-positive pivot.
-__device__ Z2* gj_inverse_hpd_pp(Z2* X, Z2* Y, int N, bool& ok) {
+// Gauss-Jordan inverse of a Hermitian positive-definite X with 2 x 2 pivot blocks
+// (a 1 x 1 block last when N is odd): half the steps of gj_inverse_hpd, and with two
+// buffers (step reads X, writes Y, then the roles swap) one barrier per step.  Step K = {k, k+1} with P = X[K][K] (Hermitian: P^{-1} from its
+// determinant), writing into Y:
+//   Y[K][K] = P^{-1},  Y[K][j] = P^{-1} X[K][j],  Y[i][K] = -X[i][K] P^{-1},
+//   Y[i][j] = X[i][j] - X[i][K] P^{-1} X[K][j]      (i, j outside K).
+// Returns the buffer holding the inverse; ok = false when a pivot block is not
+// positive definite (p00 <= 0 or det <= 0, tested after the step's barrier).
+__device__ Z2* gj_inverse_hpd_pp2(Z2* X, Z2* Y, int N, bool& ok) {
     __syncthreads();
-    for (int k = 0; k < N; ++k) {
-        const double p = X[k * N + k].re;
-        const double pinv = 1.0 / p;
+    for (int k = 0; k < N;) {
+        const int b = (k + 1 < N) ? 2 : 1;
+        const double p00 = X[k * N + k].re;
+        const double p11 = (b == 2) ? X[(k + 1) * N + k + 1].re : 1.0;
+        const Z2 p01 = (b == 2) ? X[k * N + k + 1] : Z2{0.0, 0.0};
+        const double det = p00 * p11 - (p01.re * p01.re + p01.im * p01.im);
+        const double idet = 1.0 / det;
+        const Z2 q00{p11 * idet, 0.0}, q11{p00 * idet, 0.0};
+        const Z2 q01{-p01.re * idet, -p01.im * idet}, q10{-p01.re * idet, p01.im * idet};
         for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
             const int i = row_of(e, N), j = e - i * N;
-            const Z2 xk = X[k * N + j], xe = X[e], xi = X[i * N + k];
-            const Z2 xkj = (j == k) ? Z2{1.0, 0.0} : xk;
-            const Z2 rk{xkj.re * pinv, xkj.im * pinv};
-            if (i == k) {
-                Y[e] = rk;
+            const Z2 xe = X[e], a0 = X[i * N + k], r0 = X[k * N + j];
+            const Z2 a1 = (b == 2) ? X[i * N + k + 1] : Z2{0.0, 0.0};
+            const Z2 r1 = (b == 2) ? X[(k + 1) * N + j] : Z2{0.0, 0.0};
+            const bool iK = i >= k && i < k + b, jK = j >= k && j < k + b;
+            Z2 y;
+            if (iK && jK) {
+                y = (i == k) ? ((j == k) ? q00 : q01) : ((j == k) ? q10 : q11);
+            } else if (iK) {
+                const Z2 qa = (i == k) ? q00 : q10, qb = (i == k) ? q01 : q11;
+                const Z2 u = zmul(qa, r0), v = zmul(qb, r1);
+                y = Z2{u.re + v.re, u.im + v.im};
+            } else if (jK) {
+                const Z2 qa = (j == k) ? q00 : q01, qb = (j == k) ? q10 : q11;
+                const Z2 u = zmul(a0, qa), v = zmul(a1, qb);
+                y = Z2{-(u.re + v.re), -(u.im + v.im)};
             } else {
-                const Z2 base = (j == k) ? Z2{0.0, 0.0} : xe;
-                const Z2 q = zmul(xi, rk);
-                Y[e] = Z2{base.re - q.re, base.im - q.im};
+                const Z2 t0a = zmul(q00, r0), t0b = zmul(q01, r1), t1a = zmul(q10, r0), t1b = zmul(q11, r1);
+                const Z2 t0{t0a.re + t0b.re, t0a.im + t0b.im}, t1{t1a.re + t1b.re, t1a.im + t1b.im};
+                const Z2 u = zmul(a0, t0), v = zmul(a1, t1);
+                y = Z2{xe.re - (u.re + v.re), xe.im - (u.im + v.im)};
             }
+            Y[e] = y;
         }
         __syncthreads();
-        if (!(p > 0.0) || !isfinite(p)) {
+        if (!(p00 > 0.0) || !(det > 0.0) || !isfinite(det)) {
             ok = false;
             return X;
         }
         Z2* t = X;
         X = Y;
         Y = t;
+        k += b;
     }
     ok = true;
     return X;
@@ -403,7 +424,7 @@ k_small1(const double2* __restrict__ G, const double2* __restrict__ C, double2* 
     bool ok;
     Z2* Bi;  // G^{-1}
     if (small_has_cold(N)) {
-        Bi = gj_inverse_hpd_pp(A, sm + 2 * N * N, N, ok);
+        Bi = gj_inverse_hpd_pp2(A, sm + 2 * N * N, N, ok);
     } else {
         ok = gj_inverse_hpd(A, N, rowk, colk);
         Bi = A;
