@@ -177,6 +177,14 @@ def thin_qr(M):
     return Q, R
 
 
+def thin_qr2(M):
+    """CholQR2: Alg. 2 applied twice, the second time to the Q of the first.
+    Q1 C1 = M, Q C2 = Q1, so M = Q (C2 C1).  Returns (Q, C2 C1)."""
+    Q1, C1 = thin_qr(M)
+    Q, C2 = thin_qr(Q1)
+    return Q, C2 @ C1
+
+
 def hpd_inverse(G) -> np.ndarray:
     """G^{-1} for Hermitian positive-definite G via its Cholesky factor."""
     R = cholesky_upper(G)
@@ -189,7 +197,7 @@ class SolveInfo(dict):
 
 
 def block_cg_rq(apply_A, B, tol, max_iter=100000, X0=None, ru_delta=0.0, sloppy=None,
-                trace=None):
+                trace=None, apply_sloppy=None, ru_window=0, stall_limit=0, qr_passes=1):
     """blockCGrQ (Alg. 1) with CholQR (Alg. 2) and block reliable updates (Alg. 3).
 
     apply_A: maps [N][V/2][3] -> [N][V/2][3].
@@ -204,8 +212,24 @@ def block_cg_rq(apply_A, B, tol, max_iter=100000, X0=None, ru_delta=0.0, sloppy=
     sloppy: rounding applied to the low-precision block vectors P, Q, AP (None:
       all FP64).  Y (solution) and X (update since the last reliable update)
       stay FP64 (Sec. 6, mixed precision).
+    apply_sloppy: the operator of the iteration's A P (Sec. 6: the iteration
+      runs on low-precision links); None = apply_A.  The initial and the
+      reliable-update residuals B - A Y always use apply_A (Alg. 3).
+    ru_window: adaptive reliable updates: also update when the maximum relative
+      iterated residual has not reached a new minimum since the last reliable
+      update for this many iterations (0 disables).  In exact arithmetic an
+      update changes nothing (S = C^ C_k^{-1} continues the recurrence), so
+      this only decides how often the true residual replaces the iterated one
+      -- the "more frequent / adaptive reliable updates" the paper's Sec. 8
+      names for low storage precision.
+    stall_limit: stop without convergence after this many reliable updates in
+      a row whose true residual fails to halve the smallest maximum true
+      relative residual seen so far (0 disables); info.stalled is then True.
+    qr_passes: 1 = the initial and reliable-update thin QR is CholQR (Alg. 2),
+      2 = CholQR2 (thin_qr2).  The QR inside the iteration is always Alg. 2.
     trace: optional list; per iteration a dict with beta, C (before the update),
-      S and the relative iterated residuals is appended.
+      S and the relative iterated residuals is appended (and the true relative
+      residuals at a reliable update).
 
     Returns (solution [N][V/2][3], SolveInfo).
     Raises Breakdown when a Cholesky factorisation fails before convergence.
@@ -217,6 +241,8 @@ def block_cg_rq(apply_A, B, tol, max_iter=100000, X0=None, ru_delta=0.0, sloppy=
     def A(M):
         return to_mat(apply_A(from_mat(M, vh)))
 
+    As = A if apply_sloppy is None else (lambda M: to_mat(apply_sloppy(from_mat(M, vh))))
+
     Bm = to_mat(B)
     bnorm = np.linalg.norm(Bm, axis=0)
     if np.any(bnorm == 0):
@@ -224,7 +250,8 @@ def block_cg_rq(apply_A, B, tol, max_iter=100000, X0=None, ru_delta=0.0, sloppy=
     Y = to_mat(X0).astype(np.complex128) if X0 is not None else np.zeros_like(Bm)
     X = np.zeros_like(Bm)
     R = Bm - A(Y) if X0 is not None else Bm.copy()
-    Q, C = thin_qr(R)                           # Q C = R
+    qr = thin_qr2 if qr_passes == 2 else thin_qr
+    Q, C = qr(R)                                # Q C = R
     Q = rnd(Q)
     S = np.eye(n, dtype=np.complex128)
     P = np.zeros_like(Bm)
@@ -233,12 +260,16 @@ def block_cg_rq(apply_A, B, tol, max_iter=100000, X0=None, ru_delta=0.0, sloppy=
     n_ru = 0
     history = []
     converged = False
+    stalled = False
+    best_it, best_res = 0, rho_ru               # newest minimum of the iterated residual
+    best_true, n_stall = rho_ru, 0              # smallest true residual, updates without progress
+    Y_best = Y.copy()                           # the iterate of best_true
     true_rel = np.linalg.norm(R, axis=0) / bnorm
     if rho_ru <= tol:
         converged = True
     while not converged and it < max_iter:
         P = rnd(Q + P @ S.conj().T)             # P = Q + P S^H
-        AP = rnd(A(P))
+        AP = rnd(As(P))
         G = P.conj().T @ AP                     # P^H A P
         beta = hpd_inverse(G)                   # beta = (P^H A P)^{-1}
         X = X + P @ (beta @ C)                  # X = X + P beta C
@@ -249,23 +280,37 @@ def block_cg_rq(apply_A, B, tol, max_iter=100000, X0=None, ru_delta=0.0, sloppy=
         history.append(float(relres.max()))
         rec = dict(beta=beta, C=C.copy(), relres=relres)
         conv = bool(relres.max() <= tol)
-        if conv or (ru_delta > 0 and relres.max() <= ru_delta * rho_ru):
+        if relres.max() < best_res:
+            best_it, best_res = it, float(relres.max())
+        stuck = ru_window > 0 and it - best_it >= ru_window
+        if conv or stuck or (ru_delta > 0 and relres.max() <= ru_delta * rho_ru):
             # reliable update (Alg. 3): fold X into Y, recompute the true residual
             Y = Y + X
             X = np.zeros_like(X)
             R = Bm - A(Y)
             true_rel = np.linalg.norm(R, axis=0) / bnorm
+            rec["true_rel"] = true_rel
             if conv and true_rel.max() <= tol:
                 converged = True
                 rec["S"] = None
                 if trace is not None:
                     trace.append(rec)
                 break
-            Qh, Ch = thin_qr(R)                 # Q^ C^ = R
+            n_stall = 0 if true_rel.max() <= 0.5 * best_true else n_stall + 1
+            if true_rel.max() < best_true:
+                best_true, Y_best = float(true_rel.max()), Y.copy()
+            if stall_limit > 0 and n_stall >= stall_limit:
+                stalled = True
+                rec["S"] = None
+                if trace is not None:
+                    trace.append(rec)
+                break
+            Qh, Ch = qr(R)                      # Q^ C^ = R
             S = Ch @ np.linalg.inv(C)           # S = C^ C_k^{-1}, C_k the C before this step
             C = Ch
             Q = rnd(Qh)
             rho_ru = float(true_rel.max())
+            best_it, best_res = it, rho_ru
             n_ru += 1
             rec["ru"] = True
         else:
@@ -278,7 +323,11 @@ def block_cg_rq(apply_A, B, tol, max_iter=100000, X0=None, ru_delta=0.0, sloppy=
     if not converged:
         Y = Y + X
         true_rel = np.linalg.norm(Bm - A(Y), axis=0) / bnorm
-    info = SolveInfo(iters=it, reliable_updates=n_ru, converged=converged,
+        if stall_limit > 0 and not true_rel.max() <= best_true:
+            # a failed solve returns the iterate with the smallest true residual seen
+            Y = Y_best
+            true_rel = np.linalg.norm(Bm - A(Y), axis=0) / bnorm
+    info = SolveInfo(iters=it, reliable_updates=n_ru, converged=converged, stalled=stalled,
                      true_rel_res=true_rel, history=history)
     return from_mat(Y, vh), info
 
