@@ -89,12 +89,61 @@ def load_traffic(kernel, workload_key, launch_bytes):
     return float(d["hbm_bytes_per_launch"])
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+class Progress:
+    """Prints the solver's progress to stderr at most every `every` seconds."""
+
+    def __init__(self, label, every=10.0):
+        self.label, self.every, self.last = label, every, time.perf_counter()
+
+    def __call__(self, iters, rus, relres):
+        now = time.perf_counter()
+        if now - self.last >= self.every:
+            self.last = now
+            print(f"[bench] {self.label}: {iters} iterations, {rus} reliable updates, max rel res {relres:.2e}",
+                  file=sys.stderr, flush=True)
+
+
+def kernel_rates(ctx, bcg, N, prec, Vh):
+    """Per-kernel average launch time (HIP events on the solver's stream) and
+    algorithmic GB/s of the block iteration, from the kernel timers of the last solve."""
+    rows = {}
+    for k in ("hop_oe", "hop_eo", "pass_a", "pass_b", "gram"):
+        n, ms = ctx.kernel_time(k)
+        if not n:
+            continue
+        t = ms / n
+        if k == "gram":
+            # one non-aliased (P^H AP) and one aliased (Qt^H Qt) Gram per iteration
+            b = 0.5 * (model_bytes_per_site(k, N, prec) + model_bytes_per_site(k, N, prec, aliased_gram=True)) * Vh
+        else:
+            b = model_bytes_per_site(k, N, prec) * Vh
+        rows[k] = {"us": round(t * 1e3, 1), "launches": n, "bytes_per_launch": b,
+                   "GB/s": round(b / (t * 1e-3) / 1e9, 1), "frac_hbm": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cg-steps", type=int, default=1)
+    ap.add_argument("--cg-fp64", action="store_true",
+                    help="with reduced storage, also time the FP64-storage CG baseline")
+    ap.add_argument("--no-hbm-leg", action="store_true",
+                    help="skip the 32^3x64 leg (kernel rooflines at HBM scale, oracle iteration time)")
+    ap.add_argument("--hbm-iters", type=int, default=6)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", choices=["config2", "config3"], default="config2",
@@ -123,6 +172,8 @@ def main():
 
     from paper_1710_09745_amd import bcg, synth
 
+    if args.copy_calibration:
+        copy_calibration(torch)
     if args.sweep:
         return sweep(args, bcg, synth, torch)
 
@@ -142,18 +193,11 @@ def main():
                 f"tol {tol:g}")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.copy_calibration:
-        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-        print("[bench] copy calibration: 3 x 1 GiB device copies", file=sys.stderr, flush=True)
     ctx = bcg.Context(dims, improved=True, device=dev)
     ctx.load_links(fat, lng)
     ctx.set_mass(m)
     ctx.set_solver(tol=tol, max_iter=100000, prec=prec, ru_delta=0.1)
+    ctx.set_monitor(Progress("block solve"))
     Bt = torch.from_numpy(B).to(dev)
     torch.cuda.synchronize()
     print(f"[bench] workload: {workload}", file=sys.stderr, flush=True)
@@ -193,18 +237,28 @@ def main():
     max_res = info["max_true_rel_res"]
 
     # CG baseline: N independent FP64 solves, same operator and tolerance
+    # CG baseline: N independent solves, same operator, tolerance and storage precision
+    # (double-single CG with reliable updates when the storage is not FP64)
     cg_ms, ic = None, None
+    cg64_ms, ic64 = None, None
     if not args.no_cg:
-        ctx.set_solver(tol=tol, max_iter=100000, prec="fp64", ru_delta=0.1)
-        Xc, ic = ctx.solve_cg(Bt)      # warm
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        for _ in range(args.cg_steps):
-            Xc, ic = ctx.solve_cg(Bt)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        cg_ms = (t3 - t2) * 1e3 / args.cg_steps
-        print(f"[bench] block {ms_per_step:.2f} ms/solve ({iters[-1]} iters), CG {cg_ms:.2f} ms "
+        ctx.set_monitor(Progress("CG baseline"))
+
+        def time_cg(p):
+            ctx.set_solver(tol=tol, max_iter=100000, prec=p, ru_delta=0.1)
+            _, i0 = ctx.solve_cg(Bt)      # warm
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            for _ in range(args.cg_steps):
+                _, i0 = ctx.solve_cg(Bt)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t2) * 1e3 / args.cg_steps, i0
+
+        cg_ms, ic = time_cg(prec)
+        if prec != "fp64" and args.cg_fp64:
+            cg64_ms, ic64 = time_cg("fp64")
+        ctx.set_solver(tol=tol, max_iter=100000, prec=prec, ru_delta=0.1)
+        print(f"[bench] block {ms_per_step:.2f} ms/solve ({iters[-1]} iters), CG ({prec}) {cg_ms:.2f} ms "
               f"for {N} columns ({ic['iters']} iters)", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel
@@ -229,6 +283,11 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(dims, fat, lng, m, B, tol, iters[-1], args.cpu_seconds)
+    ctx.close()
+    del Bt
+    hbm = None
+    if not args.no_hbm_leg and args.workload == "config2":
+        hbm = hbm_leg(args, bcg, synth, torch, dev)
 
     out = {
         "metric": METRIC,
@@ -249,16 +308,20 @@ def main():
         "block_iters": iters[-1],
         "block_reliable_updates": info["reliable_updates"],
         "block_max_true_rel_res": max_res,
+        "cg_storage": prec,
         "cg_ms_per_rhs": round(cg_ms / N, 4) if cg_ms else None,
         "cg_iters_per_rhs": round(ic["iters"] / N, 1) if ic else None,
+        "cg_max_true_rel_res": ic["max_true_rel_res"] if ic else None,
         "speedup_vs_cg": round(cg_ms / ms_per_step, 3) if cg_ms else None,
+        "cg_fp64_ms_per_rhs": round(cg64_ms / N, 4) if cg64_ms else None,
+        "speedup_vs_cg_fp64": round(cg64_ms / ms_per_step, 3) if cg64_ms else None,
         "roofline": roofline,
         "dslash": dslash,
         "kernel_breakdown_warmup_ms": {k: round(v["total_ms"], 3) for k, v in breakdown.items()},
         "cpu_baseline": cpu,
+        "hbm_leg": hbm,
     }
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 def sweep(args, bcg, synth, torch):
@@ -280,6 +343,7 @@ def sweep(args, bcg, synth, torch):
         B = synth.rhs(synth.make_rng(7), N, dims)
         Bt = torch.from_numpy(B).to(dev)
         ctx.set_solver(tol=1e-14, max_iter=args.sweep_iters, prec=prec, ru_delta=0.0)
+        ctx.set_stability(ru_window=0, stall_limit=0)
         ctx.solve(Bt, raise_on_error=False)                      # warm (buffers, links)
         ctx.set_profiling(bcg.KERNELS)
         ctx.profile_reset()
@@ -290,24 +354,87 @@ def sweep(args, bcg, synth, torch):
         wall = time.perf_counter() - t0
         ctx.set_profiling([])
         row = {"nrhs": N, "iters": args.sweep_iters, "solve_ms": round(wall * 1e3, 3)}
-        for k in ("hop_oe", "hop_eo", "pass_a", "pass_b", "gram"):
-            n, ms = ctx.kernel_time(k)
-            if not n:
-                continue
-            t = ms / n
-            if k == "gram":
-                # one non-aliased (P^H AP) and one aliased (Qt^H Qt) Gram per iteration
-                b = 0.5 * (model_bytes_per_site(k, N, prec) + model_bytes_per_site(k, N, prec, aliased_gram=True)) * Vh
-            else:
-                b = model_bytes_per_site(k, N, prec) * Vh
-            row[k] = {"us": round(t * 1e3, 1), "GB/s": round(b / (t * 1e-3) / 1e9, 1),
-                      "frac_hbm": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        for k, v in kernel_rates(ctx, bcg, N, prec, Vh).items():
+            row[k] = {kk: v[kk] for kk in ("us", "GB/s", "frac_hbm")}
         rows.append(row)
         print(f"[sweep] N={N}: " + json.dumps(row), file=sys.stderr, flush=True)
         del Bt
     print(json.dumps({"metric": "block-iteration kernel GB/s vs N (32^3x64 improved staggered)",
                       "storage": prec, "dims": list(dims), "rows": rows}), flush=True)
     ctx.close()
+
+
+def copy_calibration(torch):
+    """Three 1 GiB device-to-device copies: the reference kernel for scaling the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes of HBM traffic."""
+    dev = torch.device("cuda:0")
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    print("[bench] copy calibration: 3 x 1 GiB device copies", file=sys.stderr, flush=True)
+
+
+def hbm_leg(args, bcg, synth, torch, dev, N=16, prec="fp32"):
+    """Rooflines at HBM scale: a fixed number of block iterations on the 32^3 x 64
+    lattice (N = 16, FP32 storage; its working set is far beyond the 256 MB
+    Infinity Cache), every kernel timed with HIP events on the solver's stream,
+    reliable updates off so that every iteration does the same work; next to it
+    the oracle's time per block iteration on the same input (two iterations)."""
+    c = synth.CONFIGS[3]
+    dims, m = c["dims"], c["mass"]
+    Vh = synth.volume(dims) // 2
+    t0 = time.perf_counter()
+    fat, lng, B = synth.config_inputs(3, nrhs=N)
+    print(f"[bench] hbm leg: 32^3x64 inputs drawn in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    ctx = bcg.Context(dims, improved=True, device=dev)
+    ctx.load_links(fat, lng)
+    ctx.set_mass(m)
+    ctx.set_solver(tol=1e-14, max_iter=args.hbm_iters, prec=prec, ru_delta=0.0)
+    ctx.set_stability(ru_window=0, stall_limit=0)
+    Bt = torch.from_numpy(B).to(dev)
+    ctx.solve(Bt, raise_on_error=False)                      # warm (buffers, sloppy links)
+    ctx.set_profiling(bcg.KERNELS)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.solve(Bt, raise_on_error=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    rows = kernel_rates(ctx, bcg, N, prec, Vh)
+    ctx.set_profiling([])
+    ctx.close()
+    del Bt
+    dominant = max(rows, key=lambda k: rows[k]["us"] * rows[k]["launches"])
+    d = rows[dominant]
+    wkey = f"{'x'.join(str(x) for x in dims)}_n{N}_{prec}"
+    roof = {"bound": "hbm", "kernel": dominant, "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": d["frac_hbm"], "traffic": load_traffic(dominant, wkey, d["bytes_per_launch"]),
+            "bytes_per_launch": d["bytes_per_launch"], "avg_launch_ms": round(d["us"] * 1e-3, 5),
+            "launches": d["launches"]}
+    print(f"[bench] hbm leg: {args.hbm_iters} iterations in {wall * 1e3:.1f} ms; dominant {dominant} "
+          f"{d['GB/s']} GB/s", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        op = oracle.Operator(dims, fat, lng, m)
+        k = 2
+        t2 = time.perf_counter()
+        oracle.block_cg_rq(op.apply, B, 1e-30, max_iter=k)
+        t = time.perf_counter() - t2
+        cpu = {"value": round(t / k * 1e3, 1), "unit": "ms per block iteration", "cores": oracle.num_threads(),
+               "cpu": cpu_model(), "kind": "oracle",
+               "sample": f"oracle blockCGrQ (FP64) on the same 32x32x32x64 N={N} input, {k} iterations "
+                         f"(initial CholQR included) in {t:.1f} s"}
+        print(f"[bench] hbm leg: oracle {t / k:.2f} s per block iteration", file=sys.stderr, flush=True)
+    return {"workload": f"32x32x32x64 improved staggered, m={m}, N={N}, {prec} storage, "
+                        f"{args.hbm_iters} block iterations without reliable updates",
+            "ms_per_iteration": round(wall * 1e3 / args.hbm_iters, 3),
+            "roofline_hbm": roof, "kernels": {k: {kk: v[kk] for kk in ("us", "GB/s", "frac_hbm")}
+                                              for k, v in rows.items()},
+            "cpu_oracle": cpu}
 
 
 def cpu_baseline(dims, fat, lng, m, B, tol, gpu_iters, budget_s):
@@ -327,7 +454,7 @@ def cpu_baseline(dims, fat, lng, m, B, tol, gpu_iters, budget_s):
     N = B.shape[0]
     est = per_iter * gpu_iters
     return {"value": round(est * 1e3 / N, 2), "unit": "ms/RHS", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "cpu": cpu_model(), "kind": "oracle",
             "sample": f"oracle blockCGrQ (C stencil + NumPy) on the same {'x'.join(str(d) for d in dims)} "
                       f"N={N} input, first {k} iterations in {t:.1f} s, extrapolated to the GPU's "
                       f"{gpu_iters} iterations"}

@@ -59,10 +59,12 @@ typedef enum {
                                     zero right-hand-side column, unknown precision */
     BCG_ERR_HIP = -2,            /* a HIP runtime call failed */
     BCG_ERR_NOMEM = -3,          /* device or pinned host allocation failed */
-    BCG_ERR_NOT_CONVERGED = -4,  /* max_iter reached; X holds the current iterate */
+    BCG_ERR_NOT_CONVERGED = -4,  /* max_iter reached (X holds the current iterate), or
+                                    the solve stagnated (see bcg_set_stability; X holds
+                                    the best iterate) */
     BCG_ERR_BREAKDOWN = -5,      /* a Cholesky factor met a non-positive pivot before
                                     convergence (R^H R singular, Sec. 4); X holds the
-                                    current iterate */
+                                    best iterate (see bcg_set_stability) */
     BCG_ERR_STATE = -6           /* call out of order, e.g. solve before bcg_load_links */
 } bcg_status;
 
@@ -123,6 +125,17 @@ int bcg_set_solver(bcg_ctx *ctx, double tol, int max_iter, int sloppy_prec, doub
  * in, out: device [nrhs][V/2][3] complex128, must not overlap. */
 int bcg_apply(bcg_ctx *ctx, const void *in, void *out, int nrhs);
 
+/* out = A in evaluated the way the solver's iteration evaluates A P in storage
+ * precision prec (a bcg_prec): in is rounded to the storage format (one FP32
+ * scale per site and column for the 16-bit formats), T = D_oe in and
+ * A in = 4 m^2 in - D_eo T are computed with the links stored in that format,
+ * in FP32 arithmetic for every format but FP64, and T and the result are
+ * stored in the format before the result is widened to complex128.  The same
+ * kernels and launch shapes as the solver's hops for nrhs columns.  FP64 is
+ * bcg_apply.  in, out: device [nrhs][V/2][3] complex128, must not overlap.
+ * Stream-ordered. */
+int bcg_apply_prec(bcg_ctx *ctx, int prec, const void *in, void *out, int nrhs);
+
 /* One checkerboard hop out = D_{p,1-p} in (p = out_parity: 1 gives D_oe,
  * 0 gives D_eo), FP64.  in: fields on parity 1-p, out: on parity p, both
  * device [nrhs][V/2][3] complex128, must not overlap. */
@@ -136,9 +149,31 @@ int bcg_hop(bcg_ctx *ctx, int out_parity, const void *in, void *out, int nrhs);
 int bcg_solve(bcg_ctx *ctx, const void *B, void *X, int nrhs, int use_guess, bcg_stats *stats);
 
 /* The baseline: nrhs independent single right-hand-side CG solves, one after
- * the other (Sec. 7.1), on the same operator, tolerance and precision
- * (FP64 storage only).  Same arguments and returns as bcg_solve with X0 = 0. */
+ * the other (Sec. 7.1), on the same operator, tolerance and storage precision.
+ * FP64 storage: plain CG, restarted from the true residual if the iterated one
+ * met tol and the true one did not.  Any other storage (bcg_set_solver's
+ * sloppy_prec): r, p, A p and the links in that storage and FP32 arithmetic,
+ * the solution in FP64, and reliable updates as in Sec. 6 for one right-hand
+ * side (every ru_delta drop of the relative residual and at convergence: the
+ * update is folded into the FP64 solution, r = b - A x is recomputed with the
+ * FP64 operator and the recurrence continues with the same search direction),
+ * i.e. the double-single CG of Sec. 7.1.  stats->restarts counts the restarts
+ * (FP64) or reliable updates (other storage).  Same arguments and returns as
+ * bcg_solve with X0 = 0. */
 int bcg_solve_cg(bcg_ctx *ctx, const void *B, void *X, int nrhs, bcg_stats *stats);
+
+/* Pseudo-block CG, the prior work the paper contrasts with (Sec. 2): nrhs
+ * independent CG recurrences advanced together, so that every application of
+ * A serves all columns (each link read once per site for the whole block) while
+ * every column keeps its own alpha_i, beta_i and Krylov space.  A column whose
+ * iterated relative residual meets tol stops; when all have, the FP64 true
+ * residuals are checked and the columns that miss restart from theirs.  Its
+ * time against bcg_solve_cg isolates the gain of sharing the stencil, against
+ * bcg_solve the gain of sharing the Krylov space.  FP64 storage only
+ * (BCG_ERR_ARG otherwise).  stats->iters counts lockstep iterations (the
+ * largest per-column count), stats->restarts the true-residual restarts.
+ * Same arguments and returns as bcg_solve_cg. */
+int bcg_solve_pseudo(bcg_ctx *ctx, const void *B, void *X, int nrhs, bcg_stats *stats);
 
 /* Link force: the gradients w.r.t. the fat and long links of a loss L with
  * dL = -Re sum_i Lam_i^H dA X_i (X = A^{-1} B, Lam = A^{-1} dL/dX), in the
@@ -153,6 +188,40 @@ int bcg_solve_cg(bcg_ctx *ctx, const void *B, void *X, int nrhs, bcg_stats *stat
 int bcg_link_force(bcg_ctx *ctx, const void *X, const void *Lam, int nrhs, void *grad_fat,
                    void *grad_long);
 
+/* Progress callback: called on the host thread of bcg_solve / bcg_solve_cg each
+ * time the solver reads its device state (every few to some tens of
+ * iterations, and after each reliable update), with the iterations so far, the
+ * reliable updates (solve_cg: true-residual restarts) and the current maximum
+ * relative residual (iterated; the true one right after a reliable update).
+ * fn = NULL turns it off.  The callback must not call into the context. */
+typedef void (*bcg_monitor_fn)(void *user, int iters, int reliable_updates, double max_rel_res);
+int bcg_set_monitor(bcg_ctx *ctx, bcg_monitor_fn fn, void *user);
+
+/* Safeguards of the iteration in low storage precision.  The paper observes
+ * that the double-half form of the solver breaks down and leaves more
+ * frequent or adaptive reliable updates to future work (Sec. 8); these are
+ * this library's versions of them.
+ *   ru_window   > 0: also make a reliable update (Alg. 3) when the maximum
+ *               relative iterated residual has not reached a new minimum for
+ *               ru_window iterations (the iteration has stagnated, or its
+ *               residual has drifted away from the true one); 0 = only the
+ *               ru_delta rule of bcg_set_solver.  Default 100.
+ *   stall_limit > 0: give up with BCG_ERR_NOT_CONVERGED after stall_limit
+ *               reliable updates in a row whose true residual fails to halve
+ *               the smallest maximum true relative residual seen so far (the
+ *               start included); after such a stop, and after a breakdown, X
+ *               holds the iterate with the smallest maximum true residual among
+ *               those checked (a max_iter stop returns the current iterate).
+ *               0 = never (and a breakdown returns the current iterate).
+ *               Default 3.
+ *   qr_passes   1: the initial and reliable-update thin QR is one CholQR
+ *               (Alg. 2); 2: CholQR2 (Alg. 2 applied twice, the second pass on
+ *               the Q of the first; C = C2 C1).  Default 1.
+ * In exact arithmetic none of these changes the iterates: a reliable update
+ * continues the recurrence (S = C^ C_k^{-1}) and CholQR2 returns the same
+ * factors.  Returns BCG_ERR_ARG for negative values or qr_passes not 1 or 2. */
+int bcg_set_stability(bcg_ctx *ctx, int ru_window, int stall_limit, int qr_passes);
+
 /* Tuning options (launch shapes and kernel variants; results do not depend on
  * them beyond floating-point rounding order).  value 0 restores the default.
  *   BCG_OPT_HOP_TR        right-hand sides per lane in the hop (1, 2, 4, 8)
@@ -160,7 +229,11 @@ int bcg_link_force(bcg_ctx *ctx, const void *X, const void *Lam, int nrhs, void 
  *   BCG_OPT_HOP_PIPELINE  1: two folded matrices in flight per loop trip, 2: one
  *   BCG_OPT_PASS_CPT      columns per lane in the streaming passes (1, 2, 4)
  *   BCG_OPT_FUSE_GRAM     1: Gram products fused into the epilogues of the hop
- *                         and the streaming passes (G = 4 m^2 P^H P + T^H T)
+ *                         and the streaming passes (G = 4 m^2 P^H P + T^H T);
+ *                         when the epilogue's Gram tile does not fit the LDS
+ *                         budget for the chosen hop shape (e.g. FP64, N = 16
+ *                         with two lane groups), the solver uses the separate
+ *                         Gram kernels instead, with no error
  *   BCG_OPT_HOP_KERNEL    1: lane-split hop (the four lane groups of a wave take
  *                         one direction each for 16 sites), 2: site-parallel hop
  *                         (lane groups share sites, BCG_OPT_HOP_TPB); default by

@@ -220,11 +220,13 @@ def block_cg_rq(apply_A, B, tol, max_iter=100000, X0=None, ru_delta=0.0, sloppy=
       update for this many iterations (0 disables).  In exact arithmetic an
       update changes nothing (S = C^ C_k^{-1} continues the recurrence), so
       this only decides how often the true residual replaces the iterated one
-      -- the "more frequent / adaptive reliable updates" the paper's Sec. 8
-      names for low storage precision.
+      -- one form of the better reliable-update schemes that Sec. 8 leaves
+      open for low storage precision.
     stall_limit: stop without convergence after this many reliable updates in
       a row whose true residual fails to halve the smallest maximum true
-      relative residual seen so far (0 disables); info.stalled is then True.
+      relative residual seen so far (0 disables); info.stalled is then True
+      and the solution returned is the iterate with the smallest true residual
+      among those checked.
     qr_passes: 1 = the initial and reliable-update thin QR is CholQR (Alg. 2),
       2 = CholQR2 (thin_qr2).  The QR inside the iteration is always Alg. 2.
     trace: optional list; per iteration a dict with beta, C (before the update),
@@ -323,8 +325,8 @@ def block_cg_rq(apply_A, B, tol, max_iter=100000, X0=None, ru_delta=0.0, sloppy=
     if not converged:
         Y = Y + X
         true_rel = np.linalg.norm(Bm - A(Y), axis=0) / bnorm
-        if stall_limit > 0 and not true_rel.max() <= best_true:
-            # a failed solve returns the iterate with the smallest true residual seen
+        if stalled and not true_rel.max() <= best_true:
+            # a stalled solve returns the iterate with the smallest true residual seen
             Y = Y_best
             true_rel = np.linalg.norm(Bm - A(Y), axis=0) / bnorm
     info = SolveInfo(iters=it, reliable_updates=n_ru, converged=converged, stalled=stalled,

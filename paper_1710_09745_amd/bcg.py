@@ -58,6 +58,7 @@ class Stats(ctypes.Structure):
 
 
 _LIB = None
+MONITOR_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double)
 
 
 def load_library():
@@ -77,11 +78,15 @@ def load_library():
         "bcg_set_solver": ([P, D, I, I, D], I),
         "bcg_apply": ([P, P, P, I], I),
         "bcg_hop": ([P, I, P, P, I], I),
+        "bcg_apply_prec": ([P, I, P, P, I], I),
         "bcg_solve": ([P, P, P, I, I, ctypes.POINTER(Stats)], I),
         "bcg_solve_cg": ([P, P, P, I, ctypes.POINTER(Stats)], I),
+        "bcg_solve_pseudo": ([P, P, P, I, ctypes.POINTER(Stats)], I),
         "bcg_link_force": ([P, P, P, I, P, P], I),
         "bcg_set_profiling": ([P, U], I),
         "bcg_set_option": ([P, I, I], I),
+        "bcg_set_stability": ([P, I, I, I], I),
+        "bcg_set_monitor": ([P, MONITOR_FN, P], I),
         "bcg_profile_reset": ([P], I),
         "bcg_kernel_time": ([P, I, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D)], I),
         "bcg_last_error": ([P], ctypes.c_char_p),
@@ -182,6 +187,19 @@ class Context:
         self._check(self.lib.bcg_set_solver(self.h, float(tol), int(max_iter), PREC[prec],
                                             float(ru_delta)))
 
+    def set_monitor(self, fn):
+        """fn(iters, reliable_updates, max_rel_res) on every state read of a solve; None = off."""
+        if fn is None:
+            self._monitor = None
+            self._check(self.lib.bcg_set_monitor(self.h, MONITOR_FN(), None))
+            return
+        self._monitor = MONITOR_FN(lambda user, it, ru, r: fn(it, ru, r))   # kept alive here
+        self._check(self.lib.bcg_set_monitor(self.h, self._monitor, None))
+
+    def set_stability(self, ru_window=100, stall_limit=3, qr_passes=1):
+        """Adaptive reliable updates, stagnation exit and CholQR2 (bcg_set_stability)."""
+        self._check(self.lib.bcg_set_stability(self.h, int(ru_window), int(stall_limit), int(qr_passes)))
+
     # -- operator ----------------------------------------------------------------------------
     def apply(self, x, out=None):
         """A x with A = 4 m^2 - D_eo D_oe (FP64), x [N, V/2, 3]."""
@@ -189,6 +207,14 @@ class Context:
         out = torch.empty_like(x) if out is None else _vec(out, "out", vh=self.Vh)
         self._check(self.lib.bcg_apply(self.h, ctypes.c_void_p(x.data_ptr()),
                                        ctypes.c_void_p(out.data_ptr()), x.shape[0]))
+        return out
+
+    def apply_prec(self, prec, x, out=None):
+        """A x as the iteration evaluates it in storage precision prec (bcg_apply_prec)."""
+        _vec(x, "x", vh=self.Vh)
+        out = torch.empty_like(x) if out is None else _vec(out, "out", vh=self.Vh)
+        self._check(self.lib.bcg_apply_prec(self.h, PREC[prec], ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), x.shape[0]))
         return out
 
     def hop(self, out_parity, x, out=None):
@@ -230,6 +256,17 @@ class Context:
         _vec(B, "B", vh=self.Vh)
         X = torch.empty_like(B)
         rc, info = self._solve(self.lib.bcg_solve_cg, B, X)
+        if raise_on_error:
+            self._check(rc)
+        info["rc"] = rc
+        return X, info
+
+    def solve_pseudo(self, B, raise_on_error=True):
+        """Pseudo-block CG: N independent CG recurrences sharing each stencil
+        application.  Returns (X, info)."""
+        _vec(B, "B", vh=self.Vh)
+        X = torch.empty_like(B)
+        rc, info = self._solve(self.lib.bcg_solve_pseudo, B, X)
         if raise_on_error:
             self._check(rc)
         info["rc"] = rc
@@ -295,6 +332,23 @@ class BlockSolve(torch.autograd.Function):
     def backward(ctx, gX):
         (X,) = ctx.saved_tensors
         solver = ctx.solver
-        Lam, _ = solver.solve(gX.contiguous())
-        gf, gl = solver.link_force(X, Lam)
+        gX = gX.contiguous()
+        n = gX.shape[0]
+        # columns the loss does not depend on have Lam_i = 0 and add nothing to the
+        # link force (it is a sum over columns of products with Lam_i); only the
+        # others are solved (the solver rejects a zero right-hand side)
+        live = torch.nonzero(gX.reshape(n, -1).abs().amax(dim=1) > 0).flatten()
+        if live.numel() == n:
+            Lam, _ = solver.solve(gX)
+            gf, gl = solver.link_force(X, Lam)
+        else:
+            Lam = torch.zeros_like(gX)
+            if live.numel() == 0:
+                V = solver.V
+                gf = torch.zeros((4, V, 3, 3), dtype=gX.dtype, device=gX.device)
+                gl = torch.zeros_like(gf) if ctx.has_long else None
+            else:
+                Ls, _ = solver.solve(gX[live].contiguous())
+                Lam[live] = Ls
+                gf, gl = solver.link_force(X[live].contiguous(), Ls)
         return Lam, gf, (gl if ctx.has_long else None), None

@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "libbcg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["hop.hip", "blas.hip", "small.hip", "force.hip", "bcg_api.cpp"]
+SOURCES = ["hop.hip", "hop_f64.hip", "hop_f32.hip", "hop_h16.hip", "hop_b16.hip", "hop_x16.hip",
+           "blas.hip", "small.hip", "force.hip", "pseudo.hip", "bcg_api.cpp"]
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-result",
@@ -38,7 +39,7 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 5) -> str:
+def build(jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))

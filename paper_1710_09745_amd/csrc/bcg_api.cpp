@@ -49,6 +49,9 @@ struct bcg_ctx {
     int max_iter = 100000;
     Prec sloppy = Prec::FP64;
     double ru_delta = 0.1;
+    int ru_window = 100;      // adaptive reliable-update trigger (bcg_set_stability)
+    int stall_limit = 3;      // reliable updates in a row without progress before giving up
+    int qr_passes = 1;        // 1: CholQR, 2: CholQR2 in the initial and reliable-update QR
     bool links = false;
     void* W64[2] = {nullptr, nullptr};
     void* Wsl[2] = {nullptr, nullptr};
@@ -58,6 +61,8 @@ struct bcg_ctx {
     SolveState* h_state = nullptr;  // pinned
     CgState* d_cg = nullptr;
     CgState* h_cg = nullptr;        // pinned
+    PbState* d_pb = nullptr;
+    PbState* h_pb = nullptr;        // pinned
     double2* mats = nullptr;        // small matrices, 10 x [64][64]
     double2* partials = nullptr;    // 3 x GRAM_BLOCKS x 64 x 64: general / T^H T / P^H P
     double2* part_tt = nullptr;
@@ -65,7 +70,8 @@ struct bcg_ctx {
     double* nparts = nullptr;       // NORM_BLOCKS x 64 norm partials, then the CG dot partials
     long dot_off = 0;               // offset of the CG dot partials in nparts
     double* d_vec = nullptr;        // bnorm[64], true_relres[64]
-    int* d_flags = nullptr;         // ru_skip
+    int* d_flags = nullptr;         // [0] ru_skip, [64..127] pseudo-block restart flags
+    int* h_flags = nullptr;         // pinned [64]
     double* h_vec = nullptr;        // pinned [128]
     Buf work[16];
     std::string err;
@@ -78,14 +84,17 @@ struct bcg_ctx {
     // tuning options (bcg_set_option), 0 = default
     int opt[BCG_OPT_COUNT]{};
     hipStream_t cap_stream = nullptr;  // graph capture of the iteration loop
+    bcg_monitor_fn monitor = nullptr;   // progress callback (bcg_set_monitor)
+    void* monitor_user = nullptr;
 };
 
 namespace {
 
 // work buffer slots
-enum { WB_B64, WB_Y, WB_X, WB_R64, WB_T64, WB_P0, WB_P1, WB_Q0, WB_Q1, WB_AP, WB_T, WB_A0, WB_A1, WB_A2, WB_A3 };
+enum { WB_B64, WB_Y, WB_X, WB_R64, WB_T64, WB_P0, WB_P1, WB_Q0, WB_Q1, WB_AP, WB_T, WB_A0, WB_A1, WB_A2, WB_A3,
+       WB_YBEST };
 // small matrix slots
-enum { M_G, M_H, M_BETA, M_BETAC, M_C, M_CINV, M_SINV, M_SH, M_HR, M_ID, M_COUNT };
+enum { M_G, M_H, M_BETA, M_BETAC, M_C, M_CINV, M_SINV, M_SH, M_HR, M_ID, M_C2I, M_COUNT };
 
 thread_local std::string g_create_err;
 
@@ -325,6 +334,125 @@ void fill_stats(bcg_stats* st, int iters, int rus, int status, int restarts, dou
         for (int i = 0; i < N; ++i) st->true_rel_res[i] = tr[i];
 }
 
+// One CG solve per column with the vectors r, p, Ap and the links in the sloppy
+// storage and reliable updates in FP64 (Sec. 6's scheme for one right-hand side:
+// the double-single baseline of Sec. 7.1).  x holds the FP64 update since the last
+// reliable update and y the solution; a reliable update (every ru_delta drop of the
+// relative residual, and at convergence) folds x into y, recomputes r = b - A y with
+// the FP64 operator and continues with beta = ||r_true||^2 / ||r_prev||^2 and the
+// same search direction (CG's form of S = C^ C_k^{-1}).
+int cg_mixed(bcg_ctx* ctx, const double2* B64, double2* Ys, const double* bn, int N, double* tr,
+             int* total_iters, int* n_ru) {
+    const Prec ps = ctx->sloppy;
+    const int Vh = (int)ctx->Vh;
+    const long n1 = 3L * Vh;
+    hipStream_t s = ctx->stream;
+    RETCK(ensure_sloppy_links(ctx, ps));
+    const size_t b1 = store_bytes(ps, 1, 3, ctx->Vh);
+    for (int slot : {WB_A0, WB_A1, WB_A2, WB_A3}) RETCK(ensure(ctx, slot, b1));
+    void *r = W(ctx, WB_A0), *p = W(ctx, WB_A1), *Ap = W(ctx, WB_A2), *t = W(ctx, WB_A3);
+    double2 *x = Wd(ctx, WB_X), *R64 = Wd(ctx, WB_R64), *T64 = Wd(ctx, WB_T64);
+    CgState* st = ctx->d_cg;
+    const int* halt = &st->halt;
+    double* dot = ctx->nparts + ctx->dot_off;
+    const int nparts = hop_dot_blocks(ctx->g);
+    HIPCK(launch_identity(M(ctx, M_ID), 1, s));
+    int status = BCG_OK;
+    for (int i = 0; i < N; ++i) {
+        const double2* b = B64 + (long)i * n1;
+        double2* y = Ys + (long)i * n1;
+        HIPCK(launch_zero(x, n1 * 16, s));
+        HIPCK(launch_zero(y, n1 * 16, s));
+        HIPCK(launch_bmul(Prec::FP64, b, ps, nullptr, r, M(ctx, M_ID), 1, Vh, nullptr, s));
+        HIPCK(launch_copy(r, p, (long)b1, s));
+        HIPCK(launch_colnorm2(b, 1, Vh, ctx->nparts, s));
+        HIPCK(launch_cg_init(ctx->nparts, Vh, st, ctx->tol, 0, s));
+        HIPCK(launch_cg_set_ru(st, ctx->ru_delta, s));
+        double rate = -0.02, last_log = 0.0;
+        int last_it = 0, col_iters = 0;
+        tr[i] = 1.0;
+        for (;;) {
+            HIPCK(hipMemcpyAsync(ctx->h_cg, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+            RETCK(sync(ctx));
+            const CgState hc = *ctx->h_cg;
+            col_iters = hc.iters;
+            if (ctx->monitor) ctx->monitor(ctx->monitor_user, *total_iters + hc.iters, *n_ru, hc.relres);
+            if (hc.halt && hc.reason == HALT_BREAKDOWN_G) {
+                status = BCG_ERR_BREAKDOWN;
+                fail(ctx, status, "CG breakdown: p^H A p <= 0");
+                break;
+            }
+            if (hc.halt) {
+                // reliable update (also the convergence check on the true residual)
+                HIPCK(launch_fold_x(y, x, n1, s));
+                RETCK(apply64(ctx, y, R64, T64, 1, nullptr));
+                HIPCK(launch_residual(b, R64, n1, s));
+                HIPCK(launch_colnorm2(R64, 1, Vh, ctx->nparts, s));
+                HIPCK(launch_cg_ru(ctx->nparts, Vh, st, hc.reason == HALT_CONVERGED ? 1 : 0, s));
+                HIPCK(hipMemcpyAsync(ctx->h_cg, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+                RETCK(sync(ctx));
+                tr[i] = ctx->h_cg->relres;
+                if (ctx->h_cg->reason == HALT_DONE) break;
+                *n_ru += 1;
+                HIPCK(launch_bmul(Prec::FP64, R64, ps, nullptr, r, M(ctx, M_ID), 1, Vh, nullptr, s));
+                HIPCK(launch_cg_update2_s(ps, p, r, Vh, st, s));
+                last_log = std::log(std::fmax(ctx->h_cg->relres, 1e-300));
+                last_it = ctx->h_cg->iters;
+                if (ctx->h_cg->iters >= ctx->max_iter) {
+                    status = BCG_ERR_NOT_CONVERGED;
+                    fail(ctx, status, "max_iter reached in CG");
+                    break;
+                }
+                continue;
+            }
+            if (hc.iters >= ctx->max_iter) {
+                status = BCG_ERR_NOT_CONVERGED;
+                fail(ctx, status, "max_iter reached in CG");
+                break;
+            }
+            const double lg = std::log(std::fmax(hc.relres, 1e-300));
+            if (hc.iters > last_it) {
+                const double rr = (lg - last_log) / (hc.iters - last_it);
+                if (rr < 0) rate = rr;
+            }
+            last_log = lg;
+            last_it = hc.iters;
+            double target = std::log(ctx->tol);
+            if (ctx->ru_delta > 0.0) target = std::fmax(target, std::log(ctx->ru_delta * hc.rho_ru));
+            int est = (int)std::ceil((target - lg) / (rate < -1e-6 ? rate : -1e-6));
+            int chunk = est < 2 ? 2 : (est > 64 ? 64 : est);
+            if (chunk > ctx->max_iter - hc.iters) chunk = ctx->max_iter - hc.iters;
+            for (int k = 0; k < chunk; ++k) {
+                RETCK(hop(ctx, ps, 1, p, t, nullptr, 1, EPI_PLAIN_, halt));
+                RETCK(hop(ctx, ps, 0, t, Ap, p, 1, EPI_MASS_DOT_, halt, dot));
+                Prof pr(ctx, BCG_K_CG_VEC);
+                HIPCK(launch_cg_alpha(dot, nparts, st, s));
+                HIPCK(launch_cg_update1_s(ps, x, r, p, Ap, Vh, ctx->nparts, st, s));
+                HIPCK(launch_cg_beta(ctx->nparts, Vh, st, s));
+                HIPCK(launch_cg_update2_s(ps, p, r, Vh, st, s));
+            }
+        }
+        *total_iters += col_iters;
+        if (status != BCG_OK) {
+            // the column's current solution: fold the pending update and measure it
+            HIPCK(launch_fold_x(y, x, n1, s));
+            RETCK(apply64(ctx, y, R64, T64, 1, nullptr));
+            HIPCK(launch_residual(b, R64, n1, s));
+            HIPCK(launch_colnorm2(R64, 1, Vh, ctx->nparts, s));
+            HIPCK(launch_colnorm_reduce(ctx->nparts, 1, Vh, ctx->d_vec + MAXN, 1, s));
+            HIPCK(hipMemcpyAsync(ctx->h_vec, ctx->d_vec + MAXN, sizeof(double), hipMemcpyDeviceToHost, s));
+            RETCK(sync(ctx));
+            tr[i] = ctx->h_vec[0] / bn[i];
+            for (int j = i + 1; j < N; ++j) {
+                tr[j] = 1.0;
+                HIPCK(launch_zero(Ys + (long)j * n1, n1 * 16, s));
+            }
+            break;
+        }
+    }
+    return status;
+}
+
 }  // namespace
 
 // =============================================================================================
@@ -369,7 +497,10 @@ int bcg_create(bcg_ctx** out, const int dims[4], int improved, void* hip_stream)
               hipMalloc(&ctx->partials, sizeof(double2) * 3 * GRAM_BLOCKS * MAXN * MAXN) == hipSuccess &&
               hipMalloc(&ctx->nparts, sizeof(double) * ((long)NORM_BLOCKS * MAXN + hop_dot_blocks(ctx->g) + 1)) == hipSuccess &&
               hipMalloc(&ctx->d_vec, sizeof(double) * 4 * MAXN) == hipSuccess &&
-              hipMalloc(&ctx->d_flags, sizeof(int) * 16) == hipSuccess &&
+              hipMalloc(&ctx->d_flags, sizeof(int) * 128) == hipSuccess &&
+              hipMalloc(&ctx->d_pb, sizeof(PbState)) == hipSuccess &&
+              hipHostMalloc(&ctx->h_pb, sizeof(PbState)) == hipSuccess &&
+              hipHostMalloc(&ctx->h_flags, sizeof(int) * MAXN) == hipSuccess &&
               hipHostMalloc(&ctx->h_vec, sizeof(double) * 4 * MAXN) == hipSuccess;
     if (!ok) {
         bcg_destroy(ctx);
@@ -401,6 +532,9 @@ int bcg_destroy(bcg_ctx* ctx) {
     if (ctx->nparts) (void)hipFree(ctx->nparts);
     if (ctx->d_vec) (void)hipFree(ctx->d_vec);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+    if (ctx->d_pb) (void)hipFree(ctx->d_pb);
+    if (ctx->h_pb) (void)hipHostFree(ctx->h_pb);
+    if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
     if (ctx->h_vec) (void)hipHostFree(ctx->h_vec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
@@ -485,6 +619,34 @@ int bcg_apply(bcg_ctx* ctx, const void* in, void* out, int nrhs) {
     return BCG_OK;
 }
 
+int bcg_apply_prec(bcg_ctx* ctx, int prec, const void* in, void* out, int nrhs) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (!in || !out) return fail(ctx, BCG_ERR_ARG, "null vector pointer");
+    if (prec < 0 || prec > 4) return fail(ctx, BCG_ERR_ARG, "unknown precision");
+    RETCK(check_nrhs(ctx, nrhs));
+    RETCK(check_ready(ctx));
+    const Prec ps = (Prec)prec;
+    if (ps == Prec::FP64) return bcg_apply(ctx, in, out, nrhs);
+    RETCK(alloc_solve(ctx, nrhs, ps));
+    RETCK(ensure_sloppy_links(ctx, ps));
+    const int Vh = (int)ctx->Vh;
+    hipStream_t s = ctx->stream;
+    double2* I64 = Wd(ctx, WB_B64);
+    void *P = W(ctx, WB_P0), *T = W(ctx, WB_T), *AP = W(ctx, WB_AP);
+    {
+        Prof pr(ctx, BCG_K_CONVERT);
+        HIPCK(launch_canon_to_int((const double2*)in, I64, nrhs, Vh, s));
+        HIPCK(launch_identity(M(ctx, M_ID), nrhs, s));
+        HIPCK(launch_bmul(Prec::FP64, I64, ps, nullptr, P, M(ctx, M_ID), nrhs, Vh, nullptr, s));
+    }
+    RETCK(hop(ctx, ps, 1, P, T, nullptr, nrhs, EPI_PLAIN_, nullptr));
+    RETCK(hop(ctx, ps, 0, T, AP, P, nrhs, EPI_MASS_, nullptr));
+    Prof pr(ctx, BCG_K_CONVERT);
+    HIPCK(launch_bmul(ps, AP, Prec::FP64, nullptr, I64, M(ctx, M_ID), nrhs, Vh, nullptr, s));
+    HIPCK(launch_int_to_canon(I64, (double2*)out, nrhs, Vh, s));
+    return BCG_OK;
+}
+
 int bcg_hop(bcg_ctx* ctx, int out_parity, const void* in, void* out, int nrhs) {
     if (!ctx) return BCG_ERR_ARG;
     if (!in || !out) return fail(ctx, BCG_ERR_ARG, "null vector pointer");
@@ -539,6 +701,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
     const int N = nrhs;
     const Prec ps = ctx->sloppy;
     RETCK(alloc_solve(ctx, N, ps));
+    if (ctx->stall_limit > 0) RETCK(ensure(ctx, WB_YBEST, (size_t)nvec(ctx, N) * 16));
     RETCK(ensure_sloppy_links(ctx, ps));
     const int Vh = (int)ctx->Vh;
     const long n = nvec(ctx, N);
@@ -574,7 +737,10 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
         HIPCK(launch_zero(Y, n * 16, s));
         HIPCK(launch_copy(B64, R64, n * 16, s));
     }
-    HIPCK(launch_state_init(st, ctx->tol, ctx->ru_delta, d_bnorm, N, s));
+    HIPCK(launch_state_init(st, ctx->tol, ctx->ru_delta, ctx->ru_window, d_bnorm, N, s));
+    // the iterate with the smallest true residual so far, returned if the solve stalls
+    double2* Ybest = ctx->stall_limit > 0 ? Wd(ctx, WB_YBEST) : nullptr;
+    if (Ybest) HIPCK(launch_copy(Y, Ybest, n * 16, s));
     // thin QR of the initial residual (Alg. 2), Q = R C^{-1}, P = Q (S = I, P_0 = 0)
     RETCK(gram(ctx, Prec::FP64, R64, R64, N, M(ctx, M_H), nullptr));
     {
@@ -582,7 +748,22 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
         HIPCK(launch_small_init(M(ctx, M_H), M(ctx, M_C), M(ctx, M_CINV), st, N, ctx->opt[BCG_OPT_SMALL_THREADS], s));
     }
     int cur = 0;
-    {
+    if (ctx->qr_passes == 2) {
+        // CholQR2: Q1 = R C1^{-1} in FP64, Q1^H Q1 = C2^H C2, Q = Q1 C2^{-1}, C = C2 C1
+        {
+            Prof pr(ctx, BCG_K_OTHER);
+            HIPCK(launch_bmul(Prec::FP64, R64, Prec::FP64, nullptr, T64, M(ctx, M_CINV), N, Vh, halt, s));
+        }
+        RETCK(gram(ctx, Prec::FP64, T64, T64, N, M(ctx, M_H), halt));
+        {
+            Prof pr(ctx, BCG_K_SMALL);
+            HIPCK(launch_small_qr2(M(ctx, M_H), M(ctx, M_C), M(ctx, M_CINV), M(ctx, M_C2I), M(ctx, M_C), st,
+                                   (int*)&st->halt, 0, N, ctx->opt[BCG_OPT_SMALL_THREADS], s));
+        }
+        Prof pr(ctx, BCG_K_OTHER);
+        HIPCK(launch_bmul(Prec::FP64, T64, ps, nullptr, Qb[cur], M(ctx, M_C2I), N, Vh, halt, s));
+        HIPCK(launch_copy(Qb[cur], Pb[cur], (long)store_bytes(ps, N, 3, ctx->Vh), s));
+    } else {
         Prof pr(ctx, BCG_K_OTHER);
         HIPCK(launch_bmul(Prec::FP64, R64, ps, nullptr, Qb[cur], M(ctx, M_CINV), N, Vh, halt, s));
         HIPCK(launch_copy(Qb[cur], Pb[cur], (long)store_bytes(ps, N, 3, ctx->Vh), s));
@@ -607,6 +788,10 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
         status = BCG_OK;
     }
 
+    // stagnation: reliable updates in a row that fail to halve the best true residual
+    double best_true = ctx->h_state->max_relres;
+    int n_stall = 0;
+    bool want_best = false;   // stagnation or breakdown: return the best iterate, not the current one
     // convergence-rate bookkeeping for the chunk size
     double last_log = std::log(std::fmax(ctx->h_state->max_relres, 1e-300));
     int last_it = 0;
@@ -717,6 +902,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
             c = 1 - c;
         }
         RETCK(read_state(ctx));
+        if (ctx->monitor) ctx->monitor(ctx->monitor_user, hs.iters, n_ru, hs.max_relres);
         const int active = hs.iters - iters_at_resume;
         const bool halted = hs.halt != 0;
         const int reason = hs.reason;
@@ -736,6 +922,7 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
         }
         if (halted && (reason == HALT_BREAKDOWN_G || reason == HALT_BREAKDOWN_H)) {
             status = BCG_ERR_BREAKDOWN;
+            want_best = true;
             fail(ctx, status, "Cholesky breakdown before convergence (rank-deficient block)");
             break;
         }
@@ -752,14 +939,30 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
         RETCK(apply64(ctx, Y, R64, T64, N, nullptr));
         HIPCK(launch_residual(B64, R64, n, s));
         RETCK(gram(ctx, Prec::FP64, R64, R64, N, M(ctx, M_HR), nullptr));
+        const bool qr2 = ctx->qr_passes == 2;
         {
             Prof pr(ctx, BCG_K_SMALL);
             HIPCK(launch_small_ru(M(ctx, M_HR), M(ctx, M_C), M(ctx, M_CINV), M(ctx, M_SH), st, d_true,
-                                  ru_skip, reason == HALT_CONVERGED ? 1 : 0, N, ctx->opt[BCG_OPT_SMALL_THREADS], s));
+                                  ru_skip, reason == HALT_CONVERGED ? 1 : 0, qr2 ? 1 : 0, N,
+                                  ctx->opt[BCG_OPT_SMALL_THREADS], s));
+        }
+        if (qr2) {
+            // second CholQR pass on Q1 = R C^_1^{-1} (FP64), then S^ = C^ C_k^{-1}
+            {
+                Prof pr(ctx, BCG_K_OTHER);
+                HIPCK(launch_bmul(Prec::FP64, R64, Prec::FP64, nullptr, T64, M(ctx, M_CINV), N, Vh, ru_skip, s));
+            }
+            RETCK(gram(ctx, Prec::FP64, T64, T64, N, M(ctx, M_HR), ru_skip));
+            {
+                Prof pr(ctx, BCG_K_SMALL);
+                HIPCK(launch_small_qr2(M(ctx, M_HR), M(ctx, M_SH), M(ctx, M_CINV), M(ctx, M_C2I), M(ctx, M_C), st,
+                                       ru_skip, 1, N, ctx->opt[BCG_OPT_SMALL_THREADS], s));
+            }
         }
         {
             Prof pr(ctx, BCG_K_OTHER);
-            HIPCK(launch_bmul(Prec::FP64, R64, ps, nullptr, Qb[1 - cur], M(ctx, M_CINV), N, Vh, ru_skip, s));
+            if (qr2) HIPCK(launch_bmul(Prec::FP64, T64, ps, nullptr, Qb[1 - cur], M(ctx, M_C2I), N, Vh, ru_skip, s));
+            else HIPCK(launch_bmul(Prec::FP64, R64, ps, nullptr, Qb[1 - cur], M(ctx, M_CINV), N, Vh, ru_skip, s));
             HIPCK(launch_bmul(ps, Pb[cur], ps, Qb[1 - cur], Pb[1 - cur], M(ctx, M_SH), N, Vh, ru_skip, s));
         }
         if (fuse) {
@@ -774,7 +977,23 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
         }
         if (hs.halt) {
             status = BCG_ERR_BREAKDOWN;
+            want_best = true;
             fail(ctx, status, "Cholesky breakdown in the reliable update (rank-deficient residual)");
+            break;
+        }
+        // hs.max_relres is now the maximum true relative residual of Y
+        n_stall = (hs.max_relres <= 0.5 * best_true) ? 0 : n_stall + 1;
+        if (hs.max_relres < best_true) {
+            best_true = hs.max_relres;
+            if (Ybest) HIPCK(launch_copy(Y, Ybest, n * 16, s));
+        }
+        if (ctx->stall_limit > 0 && n_stall >= ctx->stall_limit) {
+            status = BCG_ERR_NOT_CONVERGED;
+            want_best = true;
+            fail(ctx, status, "stagnated: " + std::to_string(n_stall) +
+                                  " reliable updates in a row did not halve the true residual (max relative " +
+                                  std::to_string(best_true) + ")");
+            n_ru += 1;
             break;
         }
         cur = 1 - cur;
@@ -803,9 +1022,25 @@ int bcg_solve(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int use_guess, 
     HIPCK(hipMemcpyAsync(ctx->h_vec + MAXN, d_bnorm, sizeof(double) * N, hipMemcpyDeviceToHost, s));
     RETCK(sync(ctx));
     double tr[MAXN];
+    double tr_max = 0.0;
     for (int i = 0; i < N; ++i) {
         tr[i] = ctx->h_vec[i];
         if (status != BCG_OK || need_final_check) tr[i] /= ctx->h_vec[MAXN + i];
+        tr_max = std::fmax(tr_max, tr[i]);
+    }
+    if (want_best && Ybest && !(tr_max <= best_true)) {
+        // a failed solve returns the iterate with the smallest true residual seen
+        HIPCK(launch_copy(Ybest, Y, n * 16, s));
+        RETCK(apply64(ctx, Y, R64, T64, N, nullptr));
+        HIPCK(launch_residual(B64, R64, n, s));
+        RETCK(colnorms(ctx, R64, N, d_true));
+        {
+            Prof pr(ctx, BCG_K_CONVERT);
+            HIPCK(launch_int_to_canon(Y, (double2*)Xout, N, Vh, s));
+        }
+        HIPCK(hipMemcpyAsync(ctx->h_vec, d_true, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+        RETCK(sync(ctx));
+        for (int i = 0; i < N; ++i) tr[i] = ctx->h_vec[i] / ctx->h_vec[MAXN + i];
     }
     if (status == BCG_OK && need_final_check) {
         // only reached when the loop ended without a true-residual check (X0 already solved it)
@@ -825,7 +1060,6 @@ int bcg_solve_cg(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, bcg_stats* s
     if (!B || !Xout) return fail(ctx, BCG_ERR_ARG, "null vector pointer");
     RETCK(check_nrhs(ctx, nrhs));
     RETCK(check_ready(ctx));
-    if (ctx->sloppy != Prec::FP64) return fail(ctx, BCG_ERR_ARG, "the CG baseline runs in FP64 storage only");
     const auto t0 = std::chrono::steady_clock::now();
     const int N = nrhs;
     const int Vh = (int)ctx->Vh;
@@ -855,7 +1089,11 @@ int bcg_solve_cg(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, bcg_stats* s
     int total_iters = 0, restarts = 0;
     double tr[MAXN];
     const int nparts = hop_dot_blocks(ctx->g);
-    for (int i = 0; i < N && status == BCG_OK; ++i) {
+    if (ctx->sloppy != Prec::FP64) {
+        status = cg_mixed(ctx, B64, Xs, bn, N, tr, &total_iters, &restarts);
+        if (status == BCG_ERR_HIP || status == BCG_ERR_NOMEM) return status;
+    }
+    for (int i = 0; i < N && status == BCG_OK && ctx->sloppy == Prec::FP64; ++i) {
         const double2* b = B64 + (long)i * n1;
         double2* x = Xs + (long)i * n1;
         HIPCK(launch_zero(x, n1 * 16, s));
@@ -869,6 +1107,7 @@ int bcg_solve_cg(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, bcg_stats* s
             HIPCK(hipMemcpyAsync(ctx->h_cg, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
             RETCK(sync(ctx));
             const CgState hc = *ctx->h_cg;
+            if (ctx->monitor) ctx->monitor(ctx->monitor_user, total_iters + hc.iters, restarts, hc.relres);
             if (hc.halt) {
                 if (hc.reason == HALT_BREAKDOWN_G) {
                     status = BCG_ERR_BREAKDOWN;
@@ -929,6 +1168,154 @@ int bcg_solve_cg(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, bcg_stats* s
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_stats(stats, total_iters, 0, status, restarts, secs, tr, N);
     return status;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Pseudo-block CG: N independent CG recurrences sharing every application of A
+// ---------------------------------------------------------------------------------------------
+int bcg_solve_pseudo(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, bcg_stats* stats) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (!B || !Xout) return fail(ctx, BCG_ERR_ARG, "null vector pointer");
+    RETCK(check_nrhs(ctx, nrhs));
+    RETCK(check_ready(ctx));
+    if (ctx->sloppy != Prec::FP64) return fail(ctx, BCG_ERR_ARG, "the pseudo-block solver runs in FP64 storage");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int N = nrhs;
+    const int Vh = (int)ctx->Vh;
+    const long n = nvec(ctx, N);
+    hipStream_t s = ctx->stream;
+    RETCK(alloc_solve(ctx, N, Prec::FP64));
+    double2 *B64 = Wd(ctx, WB_B64), *X = Wd(ctx, WB_Y), *R = Wd(ctx, WB_R64), *T64 = Wd(ctx, WB_T64),
+            *Rt = Wd(ctx, WB_X);
+    double2 *P = Wd(ctx, WB_P0), *AP = Wd(ctx, WB_AP), *T = Wd(ctx, WB_T);
+    PbState* st = ctx->d_pb;
+    const int* halt = &st->halt;
+    int* d_restart = ctx->d_flags + 64;
+    double* d_true = ctx->d_vec + MAXN;
+    {
+        Prof pr(ctx, BCG_K_CONVERT);
+        HIPCK(launch_canon_to_int((const double2*)B, B64, N, Vh, s));
+    }
+    RETCK(colnorms(ctx, B64, N, ctx->d_vec));
+    HIPCK(hipMemcpyAsync(ctx->h_vec, ctx->d_vec, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    RETCK(sync(ctx));
+    double bn[MAXN];
+    for (int i = 0; i < N; ++i) {
+        bn[i] = ctx->h_vec[i];
+        if (!(bn[i] > 0.0) || !std::isfinite(bn[i]))
+            return fail(ctx, BCG_ERR_ARG, "right-hand side column " + std::to_string(i) + " is zero or not finite");
+    }
+    HIPCK(launch_zero(X, n * 16, s));
+    HIPCK(launch_copy(B64, R, n * 16, s));
+    HIPCK(launch_copy(B64, P, n * 16, s));
+    HIPCK(launch_colnorm2(R, N, Vh, ctx->nparts, s));
+    HIPCK(launch_pb_start(ctx->nparts, N, Vh, st, d_restart, ctx->tol, 1, s));
+    int status = BCG_OK, restarts = 0;
+    double tr[MAXN];
+    double rate = -0.02, last_log = 0.0;
+    int last_it = 0;
+    for (;;) {
+        HIPCK(hipMemcpyAsync(ctx->h_pb, st, sizeof(PbState), hipMemcpyDeviceToHost, s));
+        RETCK(sync(ctx));
+        const PbState& hp = *ctx->h_pb;
+        double mx = 0.0;
+        for (int i = 0; i < N; ++i) mx = std::fmax(mx, hp.active[i] ? hp.relres[i] : 0.0);
+        if (ctx->monitor) ctx->monitor(ctx->monitor_user, hp.iters, restarts, mx);
+        if (hp.halt && hp.reason == HALT_BREAKDOWN_G) {
+            status = BCG_ERR_BREAKDOWN;
+            fail(ctx, status, "pseudo-block CG breakdown: p^H A p <= 0");
+            break;
+        }
+        if (hp.halt) {
+            // every column met tol on its iterated residual: check the true residuals
+            RETCK(apply64(ctx, X, Rt, T64, N, nullptr));
+            HIPCK(launch_residual(B64, Rt, n, s));
+            RETCK(colnorms(ctx, Rt, N, d_true));
+            HIPCK(hipMemcpyAsync(ctx->h_vec, d_true, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+            RETCK(sync(ctx));
+            bool all = true;
+            for (int i = 0; i < N; ++i) {
+                tr[i] = ctx->h_vec[i] / bn[i];
+                ctx->h_flags[i] = tr[i] > ctx->tol ? 1 : 0;
+                all = all && !ctx->h_flags[i];
+            }
+            if (all) break;
+            if (hp.iters >= ctx->max_iter) {
+                status = BCG_ERR_NOT_CONVERGED;
+                fail(ctx, status, "max_iter reached in pseudo-block CG");
+                break;
+            }
+            // restart the columns that missed from their true residual
+            for (int i = 0; i < N; ++i)
+                if (ctx->h_flags[i]) {
+                    HIPCK(launch_copy(Rt + (long)i * 3 * Vh, R + (long)i * 3 * Vh, 3L * Vh * 16, s));
+                    HIPCK(launch_copy(Rt + (long)i * 3 * Vh, P + (long)i * 3 * Vh, 3L * Vh * 16, s));
+                }
+            HIPCK(hipMemcpyAsync(d_restart, ctx->h_flags, sizeof(int) * N, hipMemcpyHostToDevice, s));
+            HIPCK(launch_colnorm2(R, N, Vh, ctx->nparts, s));
+            HIPCK(launch_pb_start(ctx->nparts, N, Vh, st, d_restart, ctx->tol, 0, s));
+            restarts += 1;
+            continue;
+        }
+        if (hp.iters >= ctx->max_iter) {
+            status = BCG_ERR_NOT_CONVERGED;
+            fail(ctx, status, "max_iter reached in pseudo-block CG");
+            break;
+        }
+        const double lg = std::log(std::fmax(mx, 1e-300));
+        if (hp.iters > last_it) {
+            const double r = (lg - last_log) / (hp.iters - last_it);
+            if (r < 0) rate = r;
+        }
+        last_log = lg;
+        last_it = hp.iters;
+        int est = (int)std::ceil((std::log(ctx->tol) - lg) / (rate < -1e-6 ? rate : -1e-6));
+        int chunk = est < 2 ? 2 : (est > 48 ? 48 : est);
+        if (chunk > ctx->max_iter - hp.iters) chunk = ctx->max_iter - hp.iters;
+        for (int k = 0; k < chunk; ++k) {
+            RETCK(hop(ctx, Prec::FP64, 1, P, T, nullptr, N, EPI_PLAIN_, halt));
+            RETCK(hop(ctx, Prec::FP64, 0, T, AP, P, N, EPI_MASS_, halt));
+            Prof pr(ctx, BCG_K_CG_VEC);
+            HIPCK(launch_pb_dot(P, AP, N, Vh, ctx->nparts, st, s));
+            HIPCK(launch_pb_alpha(ctx->nparts, N, Vh, st, s));
+            HIPCK(launch_pb_update1(X, R, P, AP, N, Vh, ctx->nparts, st, s));
+            HIPCK(launch_pb_beta(ctx->nparts, N, Vh, st, s));
+            HIPCK(launch_pb_update2(P, R, N, Vh, st, s));
+        }
+    }
+    if (status != BCG_OK) {
+        RETCK(apply64(ctx, X, Rt, T64, N, nullptr));
+        HIPCK(launch_residual(B64, Rt, n, s));
+        RETCK(colnorms(ctx, Rt, N, d_true));
+        HIPCK(hipMemcpyAsync(ctx->h_vec, d_true, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    }
+    {
+        Prof pr(ctx, BCG_K_CONVERT);
+        HIPCK(launch_int_to_canon(X, (double2*)Xout, N, Vh, s));
+    }
+    RETCK(sync(ctx));
+    if (status != BCG_OK)
+        for (int i = 0; i < N; ++i) tr[i] = ctx->h_vec[i] / bn[i];
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(stats, ctx->h_pb->iters, 0, status, restarts, secs, tr, N);
+    return status;
+}
+
+int bcg_set_monitor(bcg_ctx* ctx, bcg_monitor_fn fn, void* user) {
+    if (!ctx) return BCG_ERR_ARG;
+    ctx->monitor = fn;
+    ctx->monitor_user = user;
+    return BCG_OK;
+}
+
+int bcg_set_stability(bcg_ctx* ctx, int ru_window, int stall_limit, int qr_passes) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (ru_window < 0 || stall_limit < 0) return fail(ctx, BCG_ERR_ARG, "ru_window and stall_limit must be >= 0");
+    if (qr_passes != 1 && qr_passes != 2) return fail(ctx, BCG_ERR_ARG, "qr_passes must be 1 or 2");
+    ctx->ru_window = ru_window;
+    ctx->stall_limit = stall_limit;
+    ctx->qr_passes = qr_passes;
+    return BCG_OK;
 }
 
 int bcg_set_option(bcg_ctx* ctx, int option, int value) {

@@ -1516,6 +1516,9 @@ k_cg_init(const double* __restrict__ partials, int P, CgState* st, double tol, i
         }
         st->tol = tol;
         st->relres = sqrt(s) / st->bnorm;
+        st->rr_prev = s;
+        st->ru_delta = 0.0;
+        st->rho_ru = st->relres;
         st->halt = (s > 0.0) ? 0 : 1;
         st->reason = (s > 0.0) ? HALT_NONE : HALT_CONVERGED;
     }
@@ -1590,10 +1593,14 @@ __global__ void __launch_bounds__(1024) k_cg_beta(const double* __restrict__ par
         st->iters += 1;
         st->relres = sqrt(rr) / st->bnorm;
         st->beta = rr / st->rr;
+        st->rr_prev = st->rr;
         st->rr = rr;
         if (st->relres <= st->tol) {
             st->halt = 1;
             st->reason = HALT_CONVERGED;
+        } else if (st->ru_delta > 0.0 && st->relres <= st->ru_delta * st->rho_ru) {
+            st->halt = 1;
+            st->reason = HALT_RU;
         }
     }
 }
@@ -1616,6 +1623,131 @@ k_cg_update2(double2* __restrict__ p, const double2* __restrict__ r, long n, con
 }
 hipError_t launch_cg_update2(double2* p, const double2* r, long n, CgState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_cg_update2, dim3(stream_grid(n)), dim3(256), 0, s, p, r, n, st);
+    return hipGetLastError();
+}
+
+// x += alpha p (x FP64); r -= alpha Ap (stored in S); partial ||r||^2 of r as stored.
+// One thread per site: the three colour components share a scale in the 16-bit formats.
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_cg_update1_s(double2* __restrict__ x, typename S::pair* __restrict__ r, float* __restrict__ rs,
+               const typename S::pair* __restrict__ p, const float* __restrict__ ps,
+               const typename S::pair* __restrict__ Ap, const float* __restrict__ Aps, int Vh,
+               double* __restrict__ partials, const CgState* __restrict__ st) {
+    if (st->halt) return;
+    using R = typename S::real;
+    const double a = st->alpha;
+    double sum = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < Vh; i += gridDim.x * 256) {
+        C2<R> pv[3], av[3], rv[3];
+        load_group<S, 3>(p, ps, Vh, 0, i, pv);
+        load_group<S, 3>(Ap, Aps, Vh, 0, i, av);
+        load_group<S, 3>(r, rs, Vh, 0, i, rv);
+        C2<double> rn[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double2 xv = x[(long)c * Vh + i];
+            xv.x = fma(a, (double)pv[c].re, xv.x);
+            xv.y = fma(a, (double)pv[c].im, xv.y);
+            x[(long)c * Vh + i] = xv;
+            rn[c] = C2<double>{fma(-a, (double)av[c].re, (double)rv[c].re), fma(-a, (double)av[c].im, (double)rv[c].im)};
+        }
+        store_group_rt<S, 3, double>(r, rs, Vh, 0, i, rn);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sum += rn[c].re * rn[c].re + rn[c].im * rn[c].im;
+    }
+    __shared__ double red[4];
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// p = r + beta p in storage S
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_cg_update2_s(typename S::pair* __restrict__ p, float* __restrict__ ps, const typename S::pair* __restrict__ r,
+               const float* __restrict__ rs, int Vh, const CgState* __restrict__ st) {
+    if (st->halt) return;
+    using R = typename S::real;
+    const double b = st->beta;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < Vh; i += gridDim.x * 256) {
+        C2<R> pv[3], rv[3];
+        load_group<S, 3>(p, ps, Vh, 0, i, pv);
+        load_group<S, 3>(r, rs, Vh, 0, i, rv);
+        C2<double> pn[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            pn[c] = C2<double>{fma(b, (double)pv[c].re, (double)rv[c].re), fma(b, (double)pv[c].im, (double)rv[c].im)};
+        store_group<S, 3, double>(p, ps, Vh, 0, i, pn);
+    }
+}
+
+template <typename S>
+static void cg_update1_t(double2* x, void* r, const void* p, const void* Ap, int Vh, double* partials,
+                         CgState* st, hipStream_t s) {
+    using P = typename S::pair;
+    hipLaunchKernelGGL(k_cg_update1_s<S>, dim3(cg_parts(Vh)), dim3(256), 0, s, x, (P*)r, scale_of<S>(r, 1, 3, Vh),
+                       (const P*)p, scale_of<S>(p, 1, 3, Vh), (const P*)Ap, scale_of<S>(Ap, 1, 3, Vh), Vh,
+                       partials, st);
+}
+template <typename S>
+static void cg_update2_t(void* p, const void* r, int Vh, CgState* st, hipStream_t s) {
+    using P = typename S::pair;
+    hipLaunchKernelGGL(k_cg_update2_s<S>, dim3(stream_grid(Vh)), dim3(256), 0, s, (P*)p, scale_of<S>(p, 1, 3, Vh),
+                       (const P*)r, scale_of<S>(r, 1, 3, Vh), Vh, st);
+}
+hipError_t launch_cg_update1_s(Prec prec, double2* x, void* r, const void* p, const void* Ap, int Vh,
+                               double* partials, CgState* st, hipStream_t s) {
+    switch (prec) {
+        case Prec::FP64: cg_update1_t<F64>(x, r, p, Ap, Vh, partials, st, s); break;
+        case Prec::FP32: cg_update1_t<F32>(x, r, p, Ap, Vh, partials, st, s); break;
+        case Prec::FP16: cg_update1_t<H16>(x, r, p, Ap, Vh, partials, st, s); break;
+        case Prec::BF16: cg_update1_t<B16>(x, r, p, Ap, Vh, partials, st, s); break;
+        case Prec::FX16: cg_update1_t<X16>(x, r, p, Ap, Vh, partials, st, s); break;
+    }
+    return hipGetLastError();
+}
+hipError_t launch_cg_update2_s(Prec prec, void* p, const void* r, int Vh, CgState* st, hipStream_t s) {
+    switch (prec) {
+        case Prec::FP64: cg_update2_t<F64>(p, r, Vh, st, s); break;
+        case Prec::FP32: cg_update2_t<F32>(p, r, Vh, st, s); break;
+        case Prec::FP16: cg_update2_t<H16>(p, r, Vh, st, s); break;
+        case Prec::BF16: cg_update2_t<B16>(p, r, Vh, st, s); break;
+        case Prec::FX16: cg_update2_t<X16>(p, r, Vh, st, s); break;
+    }
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(1024)
+k_cg_ru(const double* __restrict__ partials, int P, CgState* st, int conv_check) {
+    __shared__ double red[16];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < P; b += blockDim.x) v += partials[b];
+    const double rr = block_sum_1024(v, red);
+    if (threadIdx.x == 0) {
+        st->relres = sqrt(rr) / st->bnorm;
+        st->rho_ru = st->relres;
+        st->beta = rr / st->rr_prev;
+        st->rr = rr;
+        if (conv_check && st->relres <= st->tol) {
+            st->reason = HALT_DONE;
+        } else {
+            st->halt = 0;
+            st->reason = HALT_NONE;
+        }
+    }
+}
+hipError_t launch_cg_ru(const double* partials, int Vh, CgState* st, int conv_check, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_ru, dim3(1), dim3(1024), 0, s, partials, norm_blocks(Vh), st, conv_check);
+    return hipGetLastError();
+}
+
+__global__ void k_cg_set_ru(CgState* st, double ru_delta) {
+    if (threadIdx.x == 0) st->ru_delta = ru_delta;
+}
+hipError_t launch_cg_set_ru(CgState* st, double ru_delta, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_set_ru, dim3(1), dim3(64), 0, s, st, ru_delta);
     return hipGetLastError();
 }
 

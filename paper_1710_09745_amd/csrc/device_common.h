@@ -157,6 +157,9 @@ struct SolveState {
     double rho_ru;     // max relative residual at the last reliable update
     double tol;
     double ru_delta;
+    double best_relres; // smallest max_relres since the last reliable update (or the start)
+    int best_it;       // iteration at which best_relres was reached
+    int ru_window;     // > 0: reliable update after this many iterations without a new best_relres
     double relres[64];
     double bnorm[64];
 };

@@ -117,15 +117,55 @@ struct CgState {
     double bnorm;
     double tol;
     double relres;
+    double rr_prev;   // ||r||^2 before the last update (beta of a reliable update)
+    double ru_delta;  // > 0: reliable update when relres <= ru_delta * rho_ru (sloppy storage)
+    double rho_ru;    // relres at the last reliable update
 };
 hipError_t launch_cg_alpha(const double* dot_partials, int nparts, CgState* st, hipStream_t s);
 hipError_t launch_cg_update1(double2* x, double2* r, const double2* p, const double2* Ap, long n,
                              double* partials, CgState* st, hipStream_t s);
 hipError_t launch_cg_beta(const double* partials, long n, CgState* st, hipStream_t s);
 hipError_t launch_cg_update2(double2* p, const double2* r, long n, CgState* st, hipStream_t s);
+// mixed precision (Sec. 6 applied to CG, the double-single baseline of Sec. 7.1): r, p, Ap
+// in storage precision prec (one column, [3][Vh] groups), x FP64; partials count cg_parts(Vh)
+hipError_t launch_cg_update1_s(Prec prec, double2* x, void* r, const void* p, const void* Ap, int Vh,
+                               double* partials, CgState* st, hipStream_t s);
+hipError_t launch_cg_update2_s(Prec prec, void* p, const void* r, int Vh, CgState* st, hipStream_t s);
+// reliable update of CG from the norm partials of r = b - A y (FP64): ||r||^2, beta = ||r||^2 /
+// rr_prev, rho_ru; conv_check and relres <= tol: reason HALT_DONE (halt kept), else resume
+hipError_t launch_cg_ru(const double* partials, int Vh, CgState* st, int conv_check, hipStream_t s);
+hipError_t launch_cg_set_ru(CgState* st, double ru_delta, hipStream_t s);
 // rr = ||r||^2 from colnorm partials of a Vh-site field (restart keeps ||b|| and iters)
 hipError_t launch_cg_init(const double* partials, int Vh, CgState* st, double tol, int restart,
                           hipStream_t s);
+
+// pseudo.hip ------------------------------------------------------------------------------------
+// N independent CG recurrences sharing the block hop (FP64)
+struct PbState {
+    int halt;
+    int reason;
+    int iters;        // lockstep iterations
+    int pad;
+    double tol;
+    double rr[64];
+    double alpha[64];
+    double beta[64];
+    double relres[64];
+    double bnorm[64];
+    int active[64];
+    int col_iters[64];
+};
+hipError_t launch_pb_dot(const double2* P, const double2* AP, int N, int Vh, double* partials, const PbState* st,
+                         hipStream_t s);
+hipError_t launch_pb_alpha(const double* partials, int N, int Vh, PbState* st, hipStream_t s);
+hipError_t launch_pb_update1(double2* X, double2* R, const double2* P, const double2* AP, int N, int Vh,
+                             double* partials, const PbState* st, hipStream_t s);
+hipError_t launch_pb_beta(const double* partials, int N, int Vh, PbState* st, hipStream_t s);
+hipError_t launch_pb_update2(double2* P, const double2* R, int N, int Vh, const PbState* st, hipStream_t s);
+// (re)start: colnorm_partials from launch_colnorm2 of R; first = 1 starts every column,
+// otherwise the columns with restart[j] != 0 restart and the others stay finished
+hipError_t launch_pb_start(const double* colnorm_partials, int N, int Vh, PbState* st, const int* restart,
+                           double tol, int first, hipStream_t s);
 
 // small.hip -------------------------------------------------------------------------------------
 hipError_t small_setup();
@@ -140,11 +180,16 @@ hipError_t launch_small2(const double2* H, double2* C, double2* Sinv, double2* S
                          int N, int req, hipStream_t s);
 // reliable update from H = R^H R of the true residual: true residuals; if conv_check and
 // all <= tol: done; else C^ , C^-1, S^H = (C^ C^-1)^H, C <- C^, resume
+// first_pass: stop after C^ (in SH) and C^{-1} (in Chinv) for CholQR2
 hipError_t launch_small_ru(const double2* H, double2* C, double2* Chinv, double2* SH,
                            SolveState* st, double* true_relres, int* ru_skip, int conv_check,
-                           int N, int req, hipStream_t s);
-hipError_t launch_state_init(SolveState* st, double tol, double ru_delta, const double* bnorm,
-                             int N, hipStream_t s);
+                           int first_pass, int N, int req, hipStream_t s);
+// second CholQR pass from H2 = Q1^H Q1: Cacc <- C2 Cacc, Cinv <- Cinv C2^{-1}, C2inv <- C2^{-1};
+// ru: Cacc is the reliable update's C^ (in SH) and C holds C_k: finish the update (S^, C <- C^)
+hipError_t launch_small_qr2(const double2* H2, double2* Cacc, double2* Cinv, double2* C2inv, double2* C,
+                            SolveState* st, int* skip, int ru, int N, int req, hipStream_t s);
+hipError_t launch_state_init(SolveState* st, double tol, double ru_delta, int ru_window,
+                             const double* bnorm, int N, hipStream_t s);
 hipError_t launch_identity(double2* M, int N, hipStream_t s);
 
 // force.hip -------------------------------------------------------------------------------------

@@ -335,7 +335,7 @@ __device__ void residual_norms(const Z2* H, const Z2* C, int N, const double* bn
 
 // ---------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024)
-k_state_init(SolveState* st, double tol, double ru_delta, const double* bnorm, int N) {
+k_state_init(SolveState* st, double tol, double ru_delta, int ru_window, const double* bnorm, int N) {
     const int t = threadIdx.x;
     if (t < MAXN) {
         st->bnorm[t] = t < N ? bnorm[t] : 0.0;
@@ -350,6 +350,9 @@ k_state_init(SolveState* st, double tol, double ru_delta, const double* bnorm, i
         st->rho_ru = 1.0;
         st->tol = tol;
         st->ru_delta = ru_delta;
+        st->best_relres = 1.0;
+        st->best_it = 0;
+        st->ru_window = ru_window;
     }
 }
 
@@ -404,6 +407,8 @@ k_small_init(const double2* __restrict__ H, double2* __restrict__ C, double2* __
         }
         st->max_relres = mx;
         st->rho_ru = mx;
+        st->best_relres = mx;
+        st->best_it = st->iters;
         st->halt = 0;
         st->reason = HALT_NONE;
         st->pb_mode = PB_FULL;
@@ -490,7 +495,14 @@ k_small2(const double2* __restrict__ H, double2* __restrict__ C, double2* __rest
         st->max_relres = mx;
         st->iters += 1;
         const bool conv = mx <= st->tol;
-        const bool ru = st->ru_delta > 0.0 && mx <= st->ru_delta * st->rho_ru;
+        if (mx < st->best_relres) {
+            st->best_relres = mx;
+            st->best_it = st->iters;
+        }
+        // reliable update when the residual has dropped by ru_delta since the last one
+        // (Alg. 3), or when it has stopped reaching new minima (adaptive trigger)
+        const bool ru = (st->ru_delta > 0.0 && mx <= st->ru_delta * st->rho_ru) ||
+                        (st->ru_window > 0 && st->iters - st->best_it >= st->ru_window);
         decision = conv ? HALT_CONVERGED : (ru ? HALT_RU : HALT_NONE);
         if (decision != HALT_NONE) {
             st->halt = 1;
@@ -548,54 +560,10 @@ k_small2(const double2* __restrict__ H, double2* __restrict__ C, double2* __rest
     if (threadIdx.x == 0) st->pb_mode = PB_FULL;
 }
 
-// Reliable update from H = R^H R of the true residual R = B - A Y.
-__global__ void __launch_bounds__(1024)
-k_small_ru(const double2* __restrict__ H, double2* __restrict__ C, double2* __restrict__ Chinv,
-           double2* __restrict__ SH, SolveState* st, double* __restrict__ true_relres,
-           int* __restrict__ ru_skip, int conv_check, int N) {
-    extern __shared__ Z2 sm[];
-    Z2* A = sm;
-    Z2* W = sm + N * N;
-    __shared__ double diag[MAXN];
-    __shared__ double rel[MAXN];
-    __shared__ int done;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        rel[i] = sqrt(fmax(H[i * MAXN + i].x, 0.0)) / st->bnorm[i];
-        true_relres[i] = rel[i];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double mx = 0.0;
-        for (int i = 0; i < N; ++i) mx = fmax(mx, rel[i]);
-        done = (conv_check && mx <= st->tol) ? 1 : 0;
-        if (done) {
-            st->reason = HALT_DONE;
-            *ru_skip = 1;
-        }
-        st->rho_ru = mx;
-        st->max_relres = mx;
-    }
-    __syncthreads();
-    if (done) return;
-    load_herm(A, H, N);
-    __syncthreads();
-    for (int k = threadIdx.x; k < N; k += blockDim.x) diag[k] = A[k * N + k].re;
-    __shared__ Z2 colk[MAXN];
-    if (!chol_inv_lower(A, W, N, diag, colk)) {
-        if (threadIdx.x == 0) {
-            st->halt = 1;
-            st->reason = HALT_BREAKDOWN_H;
-            *ru_skip = 1;
-        }
-        return;
-    }
-    // C^ = L^H -> temporarily in SH; C^{-1} = (L^{-1})^H -> Chinv
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = row_of(e, N), j = e - i * N;
-        gst(SH + i * MAXN + j, (j >= i) ? zconj(A[j * N + i]) : Z2{0.0, 0.0});
-        gst(Chinv + i * MAXN + j, (j >= i) ? zconj(W[j * N + i]) : Z2{0.0, 0.0});
-    }
-    __syncthreads();
+// End of a reliable update: with C^ in SH (upper) and C_k in C, S^ = C^ C_k^{-1},
+// C <- C^, SH <- S^^H, and the iteration resumes.  A, W: LDS N x N scratch.
+__device__ void ru_set_s(double2* __restrict__ C, double2* __restrict__ SH, Z2* A, Z2* W, SolveState* st,
+                         int* __restrict__ ru_skip, int N) {
     // A <- C_k^H (lower), W <- (C_k^H)^{-1} = (C_k^{-1})^H
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
         const int i = row_of(e, N), j = e - i * N;
@@ -633,6 +601,123 @@ k_small_ru(const double2* __restrict__ H, double2* __restrict__ C, double2* __re
     }
 }
 
+// Reliable update from H = R^H R of the true residual R = B - A Y.  first_pass:
+// stop after C^ (into SH) and C^{-1} (into Chinv), for CholQR2 (k_small_qr2
+// finishes the update).
+__global__ void __launch_bounds__(1024)
+k_small_ru(const double2* __restrict__ H, double2* __restrict__ C, double2* __restrict__ Chinv,
+           double2* __restrict__ SH, SolveState* st, double* __restrict__ true_relres,
+           int* __restrict__ ru_skip, int conv_check, int first_pass, int N) {
+    extern __shared__ Z2 sm[];
+    Z2* A = sm;
+    Z2* W = sm + N * N;
+    __shared__ double diag[MAXN];
+    __shared__ double rel[MAXN];
+    __shared__ int done;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        rel[i] = sqrt(fmax(H[i * MAXN + i].x, 0.0)) / st->bnorm[i];
+        true_relres[i] = rel[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mx = 0.0;
+        for (int i = 0; i < N; ++i) mx = fmax(mx, rel[i]);
+        done = (conv_check && mx <= st->tol) ? 1 : 0;
+        if (done) {
+            st->reason = HALT_DONE;
+            *ru_skip = 1;
+        }
+        st->rho_ru = mx;
+        st->max_relres = mx;
+        st->best_relres = mx;
+        st->best_it = st->iters;
+    }
+    __syncthreads();
+    if (done) return;
+    load_herm(A, H, N);
+    __syncthreads();
+    for (int k = threadIdx.x; k < N; k += blockDim.x) diag[k] = A[k * N + k].re;
+    __shared__ Z2 colk[MAXN];
+    if (!chol_inv_lower(A, W, N, diag, colk)) {
+        if (threadIdx.x == 0) {
+            st->halt = 1;
+            st->reason = HALT_BREAKDOWN_H;
+            *ru_skip = 1;
+        }
+        return;
+    }
+    // C^ = L^H -> temporarily in SH; C^{-1} = (L^{-1})^H -> Chinv
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int i = row_of(e, N), j = e - i * N;
+        gst(SH + i * MAXN + j, (j >= i) ? zconj(A[j * N + i]) : Z2{0.0, 0.0});
+        gst(Chinv + i * MAXN + j, (j >= i) ? zconj(W[j * N + i]) : Z2{0.0, 0.0});
+    }
+    __syncthreads();
+    if (first_pass) {
+        if (threadIdx.x == 0) *ru_skip = 0;
+        return;
+    }
+    ru_set_s(C, SH, A, W, st, ru_skip, N);
+}
+
+// Second pass of CholQR2 (Alg. 2 applied to Q1 = R C1^{-1}): H2 = Q1^H Q1 =
+// C2^H C2; Cacc <- C2 C1 (C1 in Cacc), Cinv <- C1^{-1} C2^{-1}, C2inv <- C2^{-1}
+// (for Q = Q1 C2^{-1}).  ru = 1: the pass of a reliable update (Cacc is SH,
+// holding C^, and C holds C_k): the update is then finished with S^ = C^ C_k^{-1}.
+// Does nothing when *skip is set (the reliable update found convergence or broke
+// down); a breakdown pivot (below 1e-14 of the column's diagonal) halts the solve.
+__global__ void __launch_bounds__(1024)
+k_small_qr2(const double2* __restrict__ H2, double2* __restrict__ Cacc, double2* __restrict__ Cinv,
+            double2* __restrict__ C2inv, double2* __restrict__ C, SolveState* st, int* __restrict__ skip,
+            int ru, int N) {
+    if (skip && *skip) return;
+    extern __shared__ Z2 sm[];
+    Z2* A = sm;
+    Z2* W = sm + N * N;
+    __shared__ double diag[MAXN];
+    __shared__ Z2 colk[MAXN];
+    load_herm(A, H2, N);
+    __syncthreads();
+    for (int k = threadIdx.x; k < N; k += blockDim.x) diag[k] = A[k * N + k].re;
+    if (!chol_inv_lower(A, W, N, diag, colk)) {
+        if (threadIdx.x == 0) {
+            st->halt = 1;
+            st->reason = HALT_BREAKDOWN_H;
+            st->pb_mode = PB_SKIP;
+            if (skip) *skip = 1;
+        }
+        return;
+    }
+    // C2[i][m] = conj(L[m][i]) (m >= i), C2^{-1}[m][j] = conj(Z[j][m]) (j >= m)
+    Z2 cv[4], iv[4];   // N*N / blockDim <= 4 (the launcher guarantees it)
+    int cnt = 0;
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x, ++cnt) {
+        const int i = row_of(e, N), j = e - i * N;
+        Z2 a{0.0, 0.0}, b{0.0, 0.0};
+        for (int m = i; m <= j; ++m) {
+            const Z2 p = zmul(zconj(A[m * N + i]), gld(Cacc + m * MAXN + j));    // (C2 C1)[i][j]
+            const Z2 q = zmul(gld(Cinv + i * MAXN + m), zconj(W[j * N + m]));    // (C1^{-1} C2^{-1})[i][j]
+            a.re += p.re;
+            a.im += p.im;
+            b.re += q.re;
+            b.im += q.im;
+        }
+        cv[cnt] = a;
+        iv[cnt] = b;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x, ++cnt) {
+        const int i = row_of(e, N), j = e - i * N;
+        const int o = i * MAXN + j;
+        gst(Cacc + o, j >= i ? cv[cnt] : Z2{0.0, 0.0});
+        gst(Cinv + o, j >= i ? iv[cnt] : Z2{0.0, 0.0});
+        gst(C2inv + o, j >= i ? zconj(W[j * N + i]) : Z2{0.0, 0.0});
+    }
+    __syncthreads();
+    if (ru) ru_set_s(C, Cacc, A, W, st, skip, N);
+}
+
 // ---------------------------------------------------------------------------------------------
 static size_t small_lds(int N) { return (small_has_cold(N) ? 5 : 2) * (size_t)N * N * sizeof(Z2); }
 
@@ -643,6 +728,7 @@ hipError_t small_setup() {
     if ((e = hipFuncSetAttribute((const void*)k_small1, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
     if ((e = hipFuncSetAttribute((const void*)k_small2, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
     if ((e = hipFuncSetAttribute((const void*)k_small_ru, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_small_qr2, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -653,9 +739,9 @@ static int small_threads(int N, int req) {
     return N <= 16 ? 256 : 1024;
 }
 
-hipError_t launch_state_init(SolveState* st, double tol, double ru_delta, const double* bnorm, int N,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, tol, ru_delta, bnorm, N);
+hipError_t launch_state_init(SolveState* st, double tol, double ru_delta, int ru_window, const double* bnorm,
+                             int N, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, tol, ru_delta, ru_window, bnorm, N);
     return hipGetLastError();
 }
 hipError_t launch_identity(double2* M, int N, hipStream_t s) {
@@ -679,9 +765,15 @@ hipError_t launch_small2(const double2* H, double2* C, double2* Sinv, double2* S
 }
 hipError_t launch_small_ru(const double2* H, double2* C, double2* Chinv, double2* SH,
                            SolveState* st, double* true_relres, int* ru_skip, int conv_check,
-                           int N, int req, hipStream_t s) {
+                           int first_pass, int N, int req, hipStream_t s) {
     hipLaunchKernelGGL(k_small_ru, dim3(1), dim3(small_threads(N, req)), small_lds(N), s, H, C, Chinv, SH,
-                       st, true_relres, ru_skip, conv_check, N);
+                       st, true_relres, ru_skip, conv_check, first_pass, N);
+    return hipGetLastError();
+}
+hipError_t launch_small_qr2(const double2* H2, double2* Cacc, double2* Cinv, double2* C2inv, double2* C,
+                            SolveState* st, int* skip, int ru, int N, int req, hipStream_t s) {
+    hipLaunchKernelGGL(k_small_qr2, dim3(1), dim3(small_threads(N, req)), small_lds(N), s, H2, Cacc, Cinv, C2inv,
+                       C, st, skip, ru, N);
     return hipGetLastError();
 }
 

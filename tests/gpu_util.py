@@ -52,3 +52,39 @@ def kappa_bound(op: oracle.Operator, iters=60, seed=5):
         lam = float(np.linalg.norm(w) / np.linalg.norm(v))
         v = w / np.linalg.norm(w)
     return 1.05 * lam / (4 * op.mass * op.mass)
+
+
+def emulated_sloppy_apply(op: oracle.Operator, fmt, B):
+    """The oracle's A B as the solver's iteration forms it in storage format fmt:
+    input, links, T = D_oe B and the result rounded to the format (oracle.rounding),
+    arithmetic in FP64."""
+    from oracle import rounding
+    lng = rounding.round_links(op.lng, fmt) if op.improved else None
+    ops = oracle.Operator(tuple(int(d) for d in op.dims), rounding.round_links(op.fat, fmt), lng, op.mass)
+    P = rounding.round_groups(B, fmt, 1)
+    T = rounding.round_groups(ops.hop(1, P), fmt, 1)
+    AP = 4 * op.mass * op.mass * P - ops.hop(0, T)
+    return rounding.round_groups(AP, fmt, 1)
+
+
+def site_scaled_err(got, ref):
+    """max over elements of |got - ref| / (largest component of ref at that site and column)."""
+    s = np.maximum(np.abs(ref.real).max(-1, keepdims=True), np.abs(ref.imag).max(-1, keepdims=True))
+    d = np.maximum(np.abs(got.real - ref.real), np.abs(got.imag - ref.imag))
+    return float((d / s).max())
+
+
+_LINKS = {}
+
+
+def config_inputs_cached(config, nrhs):
+    """synth.config_inputs(config, nrhs=nrhs) with the links drawn once per process
+    (the 32^3 x 64 links take a while to draw); the right-hand sides are the same
+    draws as synth.config_inputs gives."""
+    if config not in _LINKS:
+        fat, lng, _ = synth.config_inputs(config, nrhs=1)
+        _LINKS[config] = (fat, lng)
+    fat, lng = _LINKS[config]
+    c = synth.CONFIGS[config]
+    B = synth.rhs(synth.make_rng(synth.seed_for(config, 1)), nrhs, c["dims"])
+    return fat, lng, B

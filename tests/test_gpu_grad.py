@@ -47,6 +47,40 @@ def test_autograd_backward_matches_oracle():
     assert np.abs(lt.grad.cpu().numpy() - rl).max() <= 1e-9 * np.abs(rl).max()
 
 
+@pytest.mark.parametrize("cols", [(0, 2), (1,), ()])
+def test_autograd_backward_with_unused_columns(cols):
+    """A loss that depends on some columns only: dL/dX is zero for the others, their
+    Lam is zero (no solve of a zero right-hand side) and the link gradients are the
+    oracle's link force of the used columns."""
+    dims = (4, 4, 4, 6)
+    m = 0.2
+    fat, lng, B = inputs(dims, True, 3, 7250)
+    ctx = context(dims, True, fat, lng, m, tol=1e-12)
+    Bt = to_dev(B).requires_grad_(True)
+    ft = to_dev(fat).requires_grad_(True)
+    lt = to_dev(lng).requires_grad_(True)
+    X = bcg.BlockSolve.apply(Bt, ft, lt, ctx)
+    mask = torch.zeros(3, dtype=torch.float64, device=DEV)
+    for c in cols:
+        mask[c] = 1.0
+    loss = torch.sum(mask[:, None, None] * torch.real(Bt.conj() * X))
+    loss.backward()
+    op = oracle.Operator(dims, fat, lng, m)
+    from test_oracle_operator import dense_A
+    Xo = oracle.from_mat(np.linalg.solve(dense_A(op), oracle.to_mat(B)), op.Vh)
+    keep = list(cols)
+    gB = np.zeros_like(B)
+    gB[keep] = 2 * Xo[keep]
+    assert np.abs(Bt.grad.cpu().numpy() - gB).max() <= 1e-9 * np.abs(Xo).max()
+    if keep:
+        rf, rl = op.link_force(Xo[keep], Xo[keep])
+    else:
+        rf, rl = np.zeros_like(fat), np.zeros_like(lng)
+    scale = max(np.abs(rf).max(), 1.0)
+    assert np.abs(ft.grad.cpu().numpy() - rf).max() <= 1e-9 * scale
+    assert np.abs(lt.grad.cpu().numpy() - rl).max() <= 1e-9 * max(np.abs(rl).max(), 1.0)
+
+
 def test_config5_backward_finite_differences():
     """Full 16^4, N = 8 workload: directional derivative of the loss along random
     complex directions of all fat links, all long links and B at once, central

@@ -9,7 +9,8 @@ import torch
 import oracle
 from paper_1710_09745_amd import synth
 
-from gpu_util import DEV, col_rel_err, context, inputs, to_dev
+from gpu_util import (DEV, col_rel_err, config_inputs_cached, context, emulated_sloppy_apply, inputs,
+                      site_scaled_err, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -82,3 +83,60 @@ def test_gauge_covariance_on_gpu():
     lhs = c2.apply(to_dev(gB)).cpu().numpy()
     rhs = np.einsum("sab,nsb->nsa", g[even], c1.apply(to_dev(B)).cpu().numpy())
     assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+
+
+# allowed deviation from the emulation, relative to the site's largest component:
+# the kernels sum the 48 complex products of a hop in FP32 (a few 2^-24 of the
+# largest term, which can exceed the result by an order of magnitude) and may round
+# T or the result to the neighbouring stored value where the emulation (FP64
+# arithmetic) rounds the other way; a flipped T propagates through the eight
+# one-hop terms of D_eo.  For the 16-bit formats that is a few storage steps (for
+# 16-bit fixed point, whose step 1/32767 is within 16x of the FP32 error of the
+# sums, eight), for FP32 a few 1e-6.  A wrong neighbour or link gives O(1).
+SLOPPY_TOL = {"fp32": 1e-5, "fp16": 4 * 2.0 ** -11, "bf16": 4 * 2.0 ** -8, "fix16": 8.0 / 32767}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16", "fix16"])
+@pytest.mark.parametrize("kernel,tr,tpb,n", [(2, 8, 2, 17), (2, 8, 2, 33), (2, 4, 2, 6), (1, 8, 0, 17),
+                                             (2, 8, 4, 16), (1, 4, 0, 3)])
+def test_sloppy_apply_matches_emulation(prec, kernel, tr, tpb, n):
+    """A P in reduced storage, as the solver's iteration forms it, against the
+    oracle's emulation of the same storage, element by element.  16x16x8x4 has
+    time slices of 1024 even sites, so the site-parallel hop with two lane groups
+    (128 sites per workgroup) takes the XCD slab order, as on 32^3 x 64; ragged N
+    leaves partial register tiles."""
+    dims = (16, 16, 8, 4)
+    fat, lng, B = inputs(dims, True, n, 9000 + n)
+    m = 0.05
+    ctx = context(dims, True, fat, lng, m)
+    for name, v in [("hop_kernel", kernel), ("hop_tr", tr), ("hop_tpb", tpb)]:
+        ctx.set_option(name, v)
+    op = oracle.Operator(dims, fat, lng, m)
+    got = ctx.apply_prec(prec, to_dev(B)).cpu().numpy()
+    ref = emulated_sloppy_apply(op, prec, B)
+    err = site_scaled_err(got, ref)
+    print(f"{prec} kernel={kernel} tr={tr} tpb={tpb} n={n}: max site-scaled error {err:.2e}")
+    assert err <= SLOPPY_TOL[prec]
+
+
+@pytest.mark.parametrize("prec,n", [("fp32", 16), ("fix16", 32), ("bf16", 32)])
+def test_full_size_sloppy_apply_sampled_sites(prec, n):
+    """The 32^3 x 64 operator in reduced storage with the default launch shape
+    (site-parallel, 8 columns per lane, two lane groups, slab order) at sampled
+    sites against the oracle's FP64 operator: the difference is the storage
+    rounding only (a wrong neighbour or link would be O(1))."""
+    c = synth.CONFIGS[3]
+    dims = c["dims"]
+    fat, lng, B = config_inputs_cached(3, n)
+    ctx = context(dims, True, fat, lng, c["mass"])
+    out = ctx.apply_prec(prec, to_dev(B))
+    op = oracle.Operator(dims, fat, lng, c["mass"])
+    sites = synth.make_rng(78).choice(synth.volume(dims) // 2, size=40, replace=False)
+    sites = np.concatenate([sites, [0, 1, synth.volume(dims) // 2 - 1]])
+    ref = op.apply_sites(B, sites)
+    got = out[:, torch.from_numpy(sites).to(DEV)].cpu().numpy()
+    del out
+    err = site_scaled_err(got, ref)
+    bound = {"fp32": 1e-5, "fix16": 2e-3, "bf16": 0.1}[prec]
+    print(f"{prec} n={n}: max site-scaled error vs FP64 {err:.2e} (bound {bound:g})")
+    assert err <= bound

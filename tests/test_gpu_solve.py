@@ -91,6 +91,63 @@ def test_cg_baseline_matches_oracle():
     assert abs(info["iters"] - its) <= 3 * 3
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fix16"])
+def test_mixed_cg_baseline_meets_tolerance(prec):
+    """Double-single (and 16-bit) CG with reliable updates: every column reaches
+    1e-8 by the oracle's FP64 operator, in about the FP64 CG iteration count."""
+    dims = (8, 8, 8, 8)
+    fat, lng, B = inputs(dims, True, 3, 6050)
+    m = 0.05
+    op = oracle.Operator(dims, fat, lng, m)
+    c64 = context(dims, True, fat, lng, m, tol=1e-8)
+    _, i64 = c64.solve_cg(to_dev(B))
+    ctx = context(dims, True, fat, lng, m, tol=1e-8, prec=prec)
+    X, info = ctx.solve_cg(to_dev(B))
+    res = true_rel_res(op, B, X.cpu().numpy())
+    print(f"{prec} CG: iters={info['iters']} reliable updates={info['restarts']} (fp64 CG {i64['iters']}) "
+          f"max res={res.max():.2e}")
+    assert res.max() <= 1e-8
+    assert np.allclose(res, info["true_rel_res"], rtol=1e-3)
+    assert info["restarts"] >= 3
+    assert info["iters"] <= 1.5 * i64["iters"] + 30
+
+
+@pytest.mark.parametrize("k", [1, 3, 7])
+def test_pseudo_block_iterates_match_oracle_cg(k):
+    """Pseudo-block CG after k lockstep iterations: every column is the oracle's
+    textbook CG iterate after k iterations (the recurrences are independent)."""
+    dims = (6, 4, 6, 6)
+    fat, lng, B = inputs(dims, True, 5, 6010)
+    m = 0.1
+    ctx = context(dims, True, fat, lng, m, tol=1e-14, max_iter=k)
+    X, info = ctx.solve_pseudo(to_dev(B), raise_on_error=False)
+    assert info["rc"] == bcg.ERR_NOT_CONVERGED and info["iters"] == k
+    op = oracle.Operator(dims, fat, lng, m)
+    Xo = np.stack([oracle.cg(op.apply, B[i], 1e-14, max_iter=k)[0] for i in range(B.shape[0])])
+    assert col_rel_err(X.cpu().numpy(), Xo).max() <= 1e-10
+
+
+@pytest.mark.parametrize("dims,n", [((8, 8, 8, 8), 8), ((6, 6, 6, 8), 17)])
+def test_pseudo_block_solve_matches_cg(dims, n):
+    """Converged pseudo-block solve: every column meets 1e-10 by the oracle's
+    operator, each in the iteration count of its own CG (the columns finish at
+    different iterations), and agrees with the CG baseline to kappa * tol."""
+    fat, lng, B = inputs(dims, True, n, 6020 + n)
+    m = 0.1
+    ctx = context(dims, True, fat, lng, m, tol=1e-10)
+    X, info = ctx.solve_pseudo(to_dev(B))
+    Xc, ic = ctx.solve_cg(to_dev(B))
+    op = oracle.Operator(dims, fat, lng, m)
+    res = true_rel_res(op, B, X.cpu().numpy())
+    print(f"pseudo-block: lockstep iters={info['iters']} restarts={info['restarts']}; "
+          f"CG total {ic['iters']} (mean {ic['iters'] / n:.1f}) max res={res.max():.2e}")
+    assert res.max() <= 1e-10
+    assert np.allclose(res, info["true_rel_res"], rtol=1e-3, atol=1e-14)
+    assert info["iters"] >= ic["iters"] / n - 2 and info["iters"] <= ic["iters"]
+    kappa = kappa_bound(op)
+    assert col_rel_err(X.cpu().numpy(), Xc.cpu().numpy()).max() <= kappa * 2e-10
+
+
 def test_n1_block_equals_cg():
     dims = (6, 6, 4, 4)
     fat, lng, B = inputs(dims, True, 1, 6100)
@@ -235,12 +292,23 @@ def test_fused_gram_path_matches_oracle(prec, n):
     tol = 1e-10 if prec == "fp64" else 1e-8
     ctx = context(dims, True, fat, lng, m, tol=tol, prec=prec)
     ctx.set_option("fuse_gram", 1)
+    if n > 8:
+        # the default two lane groups per workgroup would need more LDS than the fused
+        # epilogue may take (the solver would then quietly use the separate Grams)
+        ctx.set_option("hop_tpb", 4)
+    ctx.set_profiling(["gram"])
     X, info = ctx.solve(to_dev(B))
+    gram_launches, _ = ctx.kernel_time("gram")
+    ctx.set_profiling([])
+    # fused: separate Gram kernels only for the initial QR and the reliable updates
+    assert gram_launches < info["iters"], f"fused path not taken ({gram_launches} Gram launches)"
     op = oracle.Operator(dims, fat, lng, m)
     assert true_rel_res(op, B, X.cpu().numpy()).max() <= tol
     if prec == "fp64":
         ctx2 = context(dims, True, fat, lng, m, tol=1e-14, ru_delta=0.0, max_iter=4)
         ctx2.set_option("fuse_gram", 1)
+        if n > 8:
+            ctx2.set_option("hop_tpb", 4)
         X4, _ = ctx2.solve(to_dev(B), raise_on_error=False)
         Xo, _ = oracle.block_cg_rq(op.apply, B, 1e-14, max_iter=4)
         assert col_rel_err(X4.cpu().numpy(), Xo).max() <= 1e-10
@@ -353,10 +421,22 @@ def test_graph_replays_match_eager(dims, n):
     with eager work and host synchronisations between them) gives bit-identical
     iterates to eager launches, on two solves in a row with different column counts,
     and the solution still meets the oracle's residual bound."""
+    precs = (("fp64", 1e-10), ("fp32", 1e-8), ("bf16", 1e-8)) if n <= 16 else (("fp64", 1e-10), ("fp32", 1e-8))
+    _graph_vs_eager(dims, n, precs)
+
+
+@pytest.mark.skip(reason="BF16 storage does not converge here: on 4x4x4x8 with 33 columns (768 rows) the "
+                         "BF16 iteration diverges after its second reliable update (oracle BF16 emulation: "
+                         "iterated residual > 1e8), and the reliable-update CholQR of the diverged residual "
+                         "broke down; test_gpu_stability.py checks that the solver now stops cleanly")
+def test_graph_replays_match_eager_bf16_n33():
+    _graph_vs_eager((4, 4, 4, 8), 33, (("bf16", 1e-8),))
+
+
+def _graph_vs_eager(dims, n, precs):
     fat, lng, B = inputs(dims, True, n, 7400 + n)
     m = 0.12
     op = oracle.Operator(dims, fat, lng, m)
-    precs = (("fp64", 1e-10), ("fp32", 1e-8), ("bf16", 1e-8)) if n <= 16 else (("fp64", 1e-10), ("fp32", 1e-8))
     for prec, tol in precs:
         out = {}
         for graph in (2, 1):
