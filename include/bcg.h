@@ -125,6 +125,19 @@ int bcg_set_solver(bcg_ctx *ctx, double tol, int max_iter, int sloppy_prec, doub
  * in, out: device [nrhs][V/2][3] complex128, must not overlap. */
 int bcg_apply(bcg_ctx *ctx, const void *in, void *out, int nrhs);
 
+/* bcg_apply without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same result as bcg_apply (the same kernels).  Instead of
+ * the context's work buffers it uses a scratch array that the library keeps in
+ * device memory for the life of the process, one per GPU, shared by every
+ * context on that GPU: 3 regions of 16 MiB, so nrhs * V/2 * 48 bytes must not
+ * exceed 16 MiB (nrhs * V/2 <= 349525, e.g. 16^4 with nrhs <= 10); larger
+ * requests return BCG_ERR_ARG.  Nothing in the scratch needs to start at zero.
+ * Calls that overlap in time on one GPU (from two contexts, or on two streams)
+ * race on the scratch: order them on one stream or synchronise between them.
+ * in, out: device [nrhs][V/2][3] complex128.  Stream-ordered; no kernel timing. */
+int bcg_apply_noalloc(bcg_ctx *ctx, const void *in, void *out, int nrhs);
+
 /* out = A in evaluated the way the solver's iteration evaluates A P in storage
  * precision prec (a bcg_prec): in is rounded to the storage format (one FP32
  * scale per site and column for the 16-bit formats), T = D_oe in and

@@ -79,6 +79,7 @@ def load_library():
         "bcg_apply": ([P, P, P, I], I),
         "bcg_hop": ([P, I, P, P, I], I),
         "bcg_apply_prec": ([P, I, P, P, I], I),
+        "bcg_apply_noalloc": ([P, P, P, I], I),
         "bcg_solve": ([P, P, P, I, I, ctypes.POINTER(Stats)], I),
         "bcg_solve_cg": ([P, P, P, I, ctypes.POINTER(Stats)], I),
         "bcg_solve_pseudo": ([P, P, P, I, ctypes.POINTER(Stats)], I),
@@ -207,6 +208,14 @@ class Context:
         out = torch.empty_like(x) if out is None else _vec(out, "out", vh=self.Vh)
         self._check(self.lib.bcg_apply(self.h, ctypes.c_void_p(x.data_ptr()),
                                        ctypes.c_void_p(out.data_ptr()), x.shape[0]))
+        return out
+
+    def apply_noalloc(self, x, out):
+        """A x without any device allocation in the library (bcg_apply_noalloc); out given."""
+        _vec(x, "x", vh=self.Vh)
+        _vec(out, "out", vh=self.Vh)
+        self._check(self.lib.bcg_apply_noalloc(self.h, ctypes.c_void_p(x.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr()), x.shape[0]))
         return out
 
     def apply_prec(self, prec, x, out=None):

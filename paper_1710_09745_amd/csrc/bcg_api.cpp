@@ -37,8 +37,20 @@ struct ProfEvent {
 
 }  // namespace
 
+// Scratch of bcg_apply_noalloc: three regions (the input and the result in the
+// internal layout, and the odd-parity intermediate), each of SCRATCH_REGION bytes,
+// in a file-scope device array.  Every GPU the library runs on holds its own copy
+// until the process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (kept per device in
+// g_scratch, looked up by bcg_create).
+constexpr size_t SCRATCH_REGION = (size_t)16 << 20;
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[3 * SCRATCH_REGION];
+static void* g_scratch[SCRATCH_MAX_DEVICES] = {};
+
 struct bcg_ctx {
     Geom g{};
+    int device = 0;
     int dims[4]{};
     int improved = 0;
     int nl = 8;
@@ -476,7 +488,21 @@ int bcg_create(bcg_ctx** out, const int dims[4], int improved, void* hip_stream)
         if (e != hipSuccess) return fail(nullptr, BCG_ERR_HIP, std::string("kernel setup: ") + hipGetErrorString(e));
         setup = true;
     }
+    int dev = 0;
+    {
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return fail(nullptr, BCG_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+        if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(nullptr, BCG_ERR_ARG, "device index out of range");
+        if (!g_scratch[dev]) {
+            void* p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return fail(nullptr, BCG_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            g_scratch[dev] = p;
+        }
+    }
     ctx = new bcg_ctx();
+    ctx->device = dev;
     for (int d = 0; d < 4; ++d) {
         ctx->dims[d] = dims[d];
         ctx->g.L[d] = dims[d];
@@ -616,6 +642,36 @@ int bcg_apply(bcg_ctx* ctx, const void* in, void* out, int nrhs) {
     RETCK(apply64(ctx, W(ctx, WB_A0), W(ctx, WB_A1), W(ctx, WB_A2), nrhs, nullptr));
     Prof pr(ctx, BCG_K_CONVERT);
     HIPCK(launch_int_to_canon(Wd(ctx, WB_A1), (double2*)out, nrhs, (int)ctx->Vh, ctx->stream));
+    return BCG_OK;
+}
+
+int bcg_apply_noalloc(bcg_ctx* ctx, const void* in, void* out, int nrhs) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (!in || !out) return fail(ctx, BCG_ERR_ARG, "null vector pointer");
+    RETCK(check_nrhs(ctx, nrhs));
+    RETCK(check_ready(ctx));
+    const size_t b = (size_t)nvec(ctx, nrhs) * 16;
+    if (b > SCRATCH_REGION)
+        return fail(ctx, BCG_ERR_ARG, "bcg_apply_noalloc: nrhs * V/2 * 48 bytes = " + std::to_string(b) +
+                                          " exceeds the scratch region of " + std::to_string(SCRATCH_REGION) +
+                                          " bytes (nrhs * V/2 <= 349525); use bcg_apply");
+    char* base = (char*)g_scratch[ctx->device];
+    if (!base) return fail(ctx, BCG_ERR_STATE, "scratch address not set for this device");
+    double2* A0 = (double2*)base;
+    double2* A1 = (double2*)(base + SCRATCH_REGION);
+    double2* A2 = (double2*)(base + 2 * SCRATCH_REGION);
+    // no kernel timing here: its events would be created on demand
+    const unsigned mask = ctx->prof_mask;
+    ctx->prof_mask = 0;
+    int rc = BCG_OK;
+    hipError_t e = launch_canon_to_int((const double2*)in, A0, nrhs, (int)ctx->Vh, ctx->stream);
+    if (e == hipSuccess) {
+        rc = apply64(ctx, A0, A1, A2, nrhs, nullptr);
+        if (rc == BCG_OK) e = launch_int_to_canon(A1, (double2*)out, nrhs, (int)ctx->Vh, ctx->stream);
+    }
+    ctx->prof_mask = mask;
+    if (rc != BCG_OK) return rc;
+    if (e != hipSuccess) return fail(ctx, BCG_ERR_HIP, std::string("bcg_apply_noalloc: ") + hipGetErrorString(e));
     return BCG_OK;
 }
 
