@@ -146,9 +146,14 @@ def main():
     ap.add_argument("--hbm-iters", type=int, default=6)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["config2", "config3"], default="config2",
+    ap.add_argument("--workload", choices=["config2", "config3", "tsm192"], default="config2",
                     help="config2: 16^4, N=16, FP64 (default); config3: 32^3x64, FP32 + FP64 "
-                         "reliable updates, tol 1e-8, N from --nrhs")
+                         "reliable updates, tol 1e-8, N from --nrhs; tsm192: the paper's measurement "
+                         "workload, 192 diluted noise sources solved at 5e-6 and 2e-9 in blocks of "
+                         "--tsm-blocks (1 = the CG baseline)")
+    ap.add_argument("--tsm-lattice", default="16x16x16x48")
+    ap.add_argument("--tsm-mass", type=float, default=0.05)
+    ap.add_argument("--tsm-blocks", default="1,8,16,24,32,48,64")
     ap.add_argument("--nrhs", type=int, default=16)
     ap.add_argument("--prec", default=None, help="storage precision override (fp64/fp32/fp16/bf16/fix16)")
     ap.add_argument("--no-cg", action="store_true")
@@ -156,6 +161,9 @@ def main():
                     help="comma-separated N list: per-kernel GB/s of the 32^3x64 block iteration vs N "
                          "(a few iterations per N, FP32 storage unless --prec), one JSON line")
     ap.add_argument("--sweep-iters", type=int, default=5)
+    ap.add_argument("--sweep-lattice", default="32x32x32x64", choices=["32x32x32x64", "16x16x16x16"])
+    ap.add_argument("--hop-opts", default=None,
+                    help="launch options for the sweep, e.g. hop_kernel=2,hop_tr=8,hop_tpb=1")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device three times (the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to HBM bytes)")
@@ -176,6 +184,8 @@ def main():
         copy_calibration(torch)
     if args.sweep:
         return sweep(args, bcg, synth, torch)
+    if args.workload == "tsm192":
+        return tsm192(args, bcg, synth, torch)
 
     if args.workload == "config2":
         c = synth.CONFIGS[2]
@@ -260,6 +270,21 @@ def main():
         ctx.set_solver(tol=tol, max_iter=100000, prec=prec, ru_delta=0.1)
         print(f"[bench] block {ms_per_step:.2f} ms/solve ({iters[-1]} iters), CG ({prec}) {cg_ms:.2f} ms "
               f"for {N} columns ({ic['iters']} iters)", file=sys.stderr, flush=True)
+    # pseudo-block CG (N independent recurrences sharing each stencil application, FP64):
+    # CG -> pseudo-block is the gain of sharing the links, pseudo-block -> block CG the
+    # gain of sharing the Krylov space
+    pb_ms, ipb = None, None
+    if not args.no_cg and prec == "fp64":
+        ctx.set_monitor(Progress("pseudo-block CG"))
+        _, ipb = ctx.solve_pseudo(Bt)      # warm
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.cg_steps):
+            _, ipb = ctx.solve_pseudo(Bt)
+        torch.cuda.synchronize()
+        pb_ms = (time.perf_counter() - t2) * 1e3 / args.cg_steps
+        print(f"[bench] pseudo-block {pb_ms:.2f} ms for {N} columns ({ipb['iters']} lockstep iters)",
+              file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel
     Vh = synth.volume(dims) // 2
@@ -313,6 +338,10 @@ def main():
         "cg_iters_per_rhs": round(ic["iters"] / N, 1) if ic else None,
         "cg_max_true_rel_res": ic["max_true_rel_res"] if ic else None,
         "speedup_vs_cg": round(cg_ms / ms_per_step, 3) if cg_ms else None,
+        "pseudo_block_ms_per_rhs": round(pb_ms / N, 4) if pb_ms else None,
+        "pseudo_block_iters": ipb["iters"] if ipb else None,
+        "speedup_link_reuse": round(cg_ms / pb_ms, 3) if (pb_ms and cg_ms) else None,
+        "speedup_krylov_sharing": round(pb_ms / ms_per_step, 3) if pb_ms else None,
         "cg_fp64_ms_per_rhs": round(cg64_ms / N, 4) if cg64_ms else None,
         "speedup_vs_cg_fp64": round(cg64_ms / ms_per_step, 3) if cg64_ms else None,
         "roofline": roofline,
@@ -325,19 +354,26 @@ def main():
 
 
 def sweep(args, bcg, synth, torch):
-    """Kernel GB/s of the block iteration vs N on the 32^3x64 lattice: each N runs
-    a fixed number of block iterations (reliable updates off, so every iteration
-    does the same work) with every kernel class timed by HIP events."""
-    c = synth.CONFIGS[3]
+    """Kernel GB/s of the block iteration vs N on the 32^3x64 lattice (or the 16^4
+    one with --sweep-lattice 16x16x16x16): each N runs a fixed number of block
+    iterations (reliable updates off, so every iteration does the same work) with
+    every kernel class timed by HIP events.  --hop-opts sets launch options."""
+    cfg = 2 if args.sweep_lattice == "16x16x16x16" else 3
+    c = synth.CONFIGS[cfg]
     dims, m = c["dims"], c["mass"]
-    prec = args.prec or "fp32"
-    fat, lng, _ = synth.config_inputs(3, nrhs=1)
+    prec = args.prec or ("fp32" if cfg == 3 else "fp64")
+    fat, lng, _ = synth.config_inputs(cfg, nrhs=1)
     Vh = synth.volume(dims) // 2
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ctx = bcg.Context(dims, improved=True, device=dev)
     ctx.load_links(fat, lng)
     ctx.set_mass(m)
+    opts = {}
+    for kv in (args.hop_opts.split(",") if args.hop_opts else []):
+        k, v = kv.split("=")
+        opts[k] = int(v)
+        ctx.set_option(k, int(v))
     rows = []
     for N in [int(x) for x in args.sweep.split(",")]:
         B = synth.rhs(synth.make_rng(7), N, dims)
@@ -359,8 +395,75 @@ def sweep(args, bcg, synth, torch):
         rows.append(row)
         print(f"[sweep] N={N}: " + json.dumps(row), file=sys.stderr, flush=True)
         del Bt
-    print(json.dumps({"metric": "block-iteration kernel GB/s vs N (32^3x64 improved staggered)",
-                      "storage": prec, "dims": list(dims), "rows": rows}), flush=True)
+    print(json.dumps({"metric": f"block-iteration kernel GB/s vs N ({'x'.join(str(d) for d in dims)} improved "
+                                f"staggered)", "storage": prec, "dims": list(dims), "options": opts, "rows": rows}),
+          flush=True)
+    ctx.close()
+
+
+def tsm192(args, bcg, synth, torch):
+    """The paper's measurement workload (Sec. 7.1) on synthetic links: 192 right-hand
+    sides (24 noise sources x 8 disjoint-support subsets), every one solved twice as in
+    the truncated solver method, to 5e-6 (sloppy) and to 2e-9 (fine), in blocks of b
+    consecutive sources (b = 1: one CG solve per source, the baseline).  Prints one
+    JSON line: total time, iterations and worst true residual per block size (the
+    analogue of the paper's time-to-solution and iteration-count figures)."""
+    dims = tuple(int(x) for x in args.tsm_lattice.split("x"))
+    m = args.tsm_mass
+    prec = args.prec or "fp64"
+    blocks = [int(b) for b in args.tsm_blocks.split(",")]
+    fat = synth.fat_links(synth.make_rng(synth.seed_for(6, 0)), dims)
+    lng = synth.long_links(synth.make_rng(synth.seed_for(6, 0) + 1), dims)
+    B = synth.diluted_noise_sources(dims, 24, 8, synth.make_rng(synth.seed_for(6, 1)))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = bcg.Context(dims, improved=True, device=dev)
+    ctx.load_links(fat, lng)
+    ctx.set_mass(m)
+    Bt = torch.from_numpy(B).to(dev)
+    total = Bt.shape[0]
+    rows = []
+    for b in blocks:
+        if total % b:
+            continue
+        row = {"block": b, "solves": total // b}
+        for name, tol in (("sloppy", 5e-6), ("fine", 2e-9)):
+            ctx.set_solver(tol=tol, max_iter=100000, prec=prec, ru_delta=0.1)
+            ctx.set_monitor(Progress(f"tsm192 b={b} {name}"))
+            if b == 1:
+                ctx.solve_cg(Bt[:1])          # warm
+            else:
+                ctx.solve(Bt[:b].contiguous(), raise_on_error=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its = rhs_its = 0
+            worst = 0.0
+            fails = 0
+            for j in range(0, total, b):
+                Bj = Bt[j:j + b].contiguous()
+                if b == 1:
+                    _, info = ctx.solve_cg(Bj, raise_on_error=False)
+                    its += info["iters"]
+                    rhs_its += info["iters"]
+                else:
+                    _, info = ctx.solve(Bj, raise_on_error=False)
+                    its += info["iters"]
+                    rhs_its += info["iters"] * b
+                worst = max(worst, info["max_true_rel_res"])
+                fails += info["rc"] != 0
+            torch.cuda.synchronize()
+            row[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 1), "iters": its, "rhs_iters": rhs_its,
+                         "max_true_rel_res": worst, "failed_solves": fails}
+        row["total_ms"] = round(row["sloppy"]["ms"] + row["fine"]["ms"], 1)
+        rows.append(row)
+        print(f"[tsm192] b={b}: {row['total_ms']} ms (sloppy {row['sloppy']['iters']} + fine "
+              f"{row['fine']['iters']} iterations)", file=sys.stderr, flush=True)
+    base = next((r["total_ms"] for r in rows if r["block"] == 1), None)
+    for r in rows:
+        r["speedup_vs_cg"] = round(base / r["total_ms"], 3) if base else None
+    print(json.dumps({"metric": "total time for 192 diluted sources, sloppy 5e-6 + fine 2e-9, vs block size",
+                      "lattice": list(dims), "mass": m, "storage": prec, "data": "synthetic",
+                      "rows": rows}), flush=True)
     ctx.close()
 
 

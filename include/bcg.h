@@ -254,12 +254,15 @@ int bcg_set_stability(bcg_ctx *ctx, int ru_window, int stall_limit, int qr_passe
  *   BCG_OPT_GRAM_KERNEL   1: Gram products on the matrix cores (FP64 MFMA) for
  *                         N > 8, 2: on the vector ALUs
  *   BCG_OPT_SMALL_THREADS threads (64, 256, 1024) of the one-workgroup N x N
- *                         kernels, used when N^2 <= 4 x threads
+ *                         kernels, used when N^2 <= 4 x threads; 0 (default):
+ *                         256 for N <= 16, else 1024
  *   BCG_OPT_SITE_ORDER    1: workgroups walk the lattice so that XCD x takes the
  *                         x-th eighth of every time slice and all XCDs sweep the
  *                         slices together, 2: plain lexicographic order
  *   BCG_OPT_PASS_KERNEL   1: passes A and B on the matrix cores (FP64 MFMA) for
- *                         16 < N <= 32 in FP32 / FP64 storage, otherwise vector
+ *                         16 < N <= 32 in FP32 / FP64 storage, and for
+ *                         32 < N <= 64 in FP32 storage (FP32 MFMA for the FP32
+ *                         products, FP64 MFMA for the X increment), otherwise vector
  *                         ALUs (pass B with its N x N coefficients staged in LDS);
  *                         2: vector kernels with LDS-staged coefficients (both
  *                         passes); 3: vector kernels reading the coefficients
@@ -267,10 +270,16 @@ int bcg_set_stability(bcg_ctx *ctx, int ru_window, int stall_limit, int qr_passe
  *   BCG_OPT_GRAPH         1: the solver iterations run as replays of a captured
  *                         HIP graph of two iterations; 0 (default), 2: eager
  *                         launches (always eager while kernel profiling is on)
+ *   BCG_OPT_HOP_SCHED     site-parallel hop: 1 static slab order; 2, 3, 4, 5:
+ *                         per-XCD task queues (the workgroups of each XCD take
+ *                         consecutive blocks of neighbouring lattice cells, then
+ *                         help drain the other XCDs' queues) with 1, 2, 4 or 8
+ *                         workgroups per CU in a persistent grid
  * Returns BCG_ERR_ARG for an unknown option. */
 enum { BCG_OPT_HOP_TR = 0, BCG_OPT_HOP_TPB = 1, BCG_OPT_HOP_PIPELINE = 2, BCG_OPT_PASS_CPT = 3,
        BCG_OPT_FUSE_GRAM = 4, BCG_OPT_HOP_KERNEL = 5, BCG_OPT_GRAM_KERNEL = 6, BCG_OPT_SMALL_THREADS = 7,
-       BCG_OPT_SITE_ORDER = 8, BCG_OPT_PASS_KERNEL = 9, BCG_OPT_GRAPH = 10, BCG_OPT_COUNT = 11 };
+       BCG_OPT_SITE_ORDER = 8, BCG_OPT_PASS_KERNEL = 9, BCG_OPT_GRAPH = 10, BCG_OPT_HOP_SCHED = 11,
+       BCG_OPT_COUNT = 12 };
 int bcg_set_option(bcg_ctx *ctx, int option, int value);
 
 /* Per-kernel timing with HIP events on the context's stream.  mask: bit set of

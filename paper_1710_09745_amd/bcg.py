@@ -30,7 +30,7 @@ STATUS_NAMES = {OK: "ok", ERR_ARG: "bad argument", ERR_HIP: "HIP error", ERR_NOM
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "fix16": 4}
 OPTIONS = {"hop_tr": 0, "hop_tpb": 1, "hop_pipeline": 2, "pass_cpt": 3, "fuse_gram": 4, "hop_kernel": 5, "gram_kernel": 6,
            "small_threads": 7, "site_order": 8,
-           "pass_kernel": 9, "graph": 10}
+           "pass_kernel": 9, "graph": 10, "hop_sched": 11}
 KERNELS = ["hop_oe", "hop_eo", "gram", "reduce", "small", "pass_a", "pass_b", "cg_vec",
            "convert", "other"]
 MAX_RHS = 64

@@ -83,6 +83,7 @@ struct bcg_ctx {
     long dot_off = 0;               // offset of the CG dot partials in nparts
     double* d_vec = nullptr;        // bnorm[64], true_relres[64]
     int* d_flags = nullptr;         // [0] ru_skip, [64..127] pseudo-block restart flags
+    int* hopq = nullptr;            // per-XCD task queues of the hop (16 ints, kept at zero between launches)
     int* h_flags = nullptr;         // pinned [64]
     double* h_vec = nullptr;        // pinned [128]
     Buf work[16];
@@ -241,7 +242,7 @@ int bps64(bcg_ctx* ctx) { return blocks_per_slice(ctx->g, 64); }
 
 HopShape shape(bcg_ctx* ctx, Prec p, int N, bool fused) {
     return hop_shape(p, N, ctx->opt[BCG_OPT_HOP_TR], ctx->opt[BCG_OPT_HOP_TPB], ctx->opt[BCG_OPT_HOP_PIPELINE],
-                     ctx->opt[BCG_OPT_HOP_KERNEL], ctx->g, fused);
+                     ctx->opt[BCG_OPT_HOP_KERNEL], ctx->g, fused, ctx->opt[BCG_OPT_HOP_SCHED]);
 }
 
 int hop(bcg_ctx* ctx, Prec p, int out_parity, const void* in, void* out, const void* ctr, int N,
@@ -251,7 +252,7 @@ int hop(bcg_ctx* ctx, Prec p, int out_parity, const void* in, void* out, const v
     if (epi == EPI_MASS_DOT_) h = HopShape{1, 1, h.pf, 1};  // the CG path: one column, direction split
     Prof pr(ctx, out_parity == 1 ? BCG_K_HOP_OE : BCG_K_HOP_EO);
     HIPCK(launch_hop(p, ctx->nl, Wp, in, out, ctr, 4.0 * ctx->mass * ctx->mass, N, ctx->g,
-                     out_parity, epi, h, halt, dot, partials, ctx->stream));
+                     out_parity, epi, h, halt, dot, partials, ctx->hopq, ctx->stream));
     return BCG_OK;
 }
 
@@ -525,6 +526,8 @@ int bcg_create(bcg_ctx** out, const int dims[4], int improved, void* hip_stream)
               hipMalloc(&ctx->d_vec, sizeof(double) * 4 * MAXN) == hipSuccess &&
               hipMalloc(&ctx->d_flags, sizeof(int) * 128) == hipSuccess &&
               hipMalloc(&ctx->d_pb, sizeof(PbState)) == hipSuccess &&
+              hipMalloc(&ctx->hopq, sizeof(int) * 16) == hipSuccess &&
+              hipMemset(ctx->hopq, 0, sizeof(int) * 16) == hipSuccess &&
               hipHostMalloc(&ctx->h_pb, sizeof(PbState)) == hipSuccess &&
               hipHostMalloc(&ctx->h_flags, sizeof(int) * MAXN) == hipSuccess &&
               hipHostMalloc(&ctx->h_vec, sizeof(double) * 4 * MAXN) == hipSuccess;
@@ -559,6 +562,7 @@ int bcg_destroy(bcg_ctx* ctx) {
     if (ctx->d_vec) (void)hipFree(ctx->d_vec);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     if (ctx->d_pb) (void)hipFree(ctx->d_pb);
+    if (ctx->hopq) (void)hipFree(ctx->hopq);
     if (ctx->h_pb) (void)hipHostFree(ctx->h_pb);
     if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
     if (ctx->h_vec) (void)hipHostFree(ctx->h_vec);

@@ -762,6 +762,74 @@ k_pass_a_mfma(typename S::pair* __restrict__ Q, const typename S::pair* __restri
     }
 }
 
+// Pass A on the matrix cores for FP32 storage and 32 < N <= 64: the layout of
+// k_pass_a_mfma with beta staged in FP32 (32 KB) and the products on
+// v_mfma_f32_16x16x4f32 (FP32 storage, FP32 arithmetic, as the vector kernel).
+#define F32_ACC_ROW(m, l) (4 * ((l) >> 4) + (m))
+__global__ void __launch_bounds__(256)
+k_pass_a_mfma32(float2* __restrict__ Q, const float2* __restrict__ AP, const double2* __restrict__ beta, int N,
+                int Vh, const int* __restrict__ halt) {
+    constexpr int NT = 4, NQ = 16, NP = 64;
+    typedef float fvec4 __attribute__((ext_vector_type(4)));
+    extern __shared__ float2 cb[];  // [NP][NP] beta in FP32, zero outside N x N
+    if (halt != nullptr && *halt) return;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r16 = lane & 15, k4 = lane >> 4;
+    for (int e = threadIdx.x; e < NP * NP; e += 256) {
+        const int l = e / NP, j = e % NP;
+        const double2 b = (l < N && j < N) ? beta[l * MAXN + j] : make_double2(0.0, 0.0);
+        cb[e] = make_float2((float)b.x, (float)b.y);
+    }
+    __syncthreads();
+    const long nrb = (long)((Vh + 15) / 16) * 3;
+    const long ngroups = (nrb + 3) / 4;
+    for (long g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const long rb0 = g * 4 + w;
+        const bool rb_ok = rb0 < nrb;
+        const long rb = rb_ok ? rb0 : nrb - 1;
+        const int c = (int)(rb % 3);
+        const int site = (int)(rb / 3) * 16 + r16;
+        const bool live = rb_ok && site < Vh;
+        const int si = site < Vh ? site : Vh - 1;
+        float ar[NQ], ai[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int l = 4 * q + k4;
+            const bool ok = l < N;
+            const float2 a = AP[((long)(ok ? l : N - 1) * 3 + c) * Vh + si];
+            ar[q] = ok ? a.x : 0.0f;
+            ai[q] = ok ? a.y : 0.0f;
+        }
+#pragma unroll 1
+        for (int jt = 0; jt < NT; ++jt) {
+            if (jt * 16 >= N) break;
+            const int jo = jt * 16 + r16;
+            fvec4 yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int l = 4 * q + k4;
+                const float2 m = cb[l * NP + jo];
+                yr = __builtin_amdgcn_mfma_f32_16x16x4f32(m.x, ar[q], yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x4f32(m.x, ai[q], yi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_16x16x4f32(-m.y, ai[q], yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x4f32(m.y, ar[q], yi, 0, 0, 0);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int j = jt * 16 + F32_ACC_ROW(m, lane);
+                if (!live || j >= N) continue;
+                const long o = ((long)j * 3 + c) * Vh + site;
+                float2 qv = Q[o];
+                qv.x -= yr[m];
+                qv.y -= yi[m];
+                Q[o] = qv;
+            }
+        }
+    }
+}
+#undef F32_ACC_ROW
+
 hipError_t launch_pass_a(Prec prec, void* Q, const void* AP, const double2* beta, int N, int Vh,
                          const int* halt, double2* partials, int cpt, int bps, int kernel, hipStream_t s) {
     if (partials != nullptr && fused_tile_bytes(prec, N) == 0) return hipErrorInvalidValue;
@@ -776,6 +844,13 @@ hipError_t launch_pass_a(Prec prec, void* Q, const void* AP, const double2* beta
         else
             hipLaunchKernelGGL((k_pass_a_mfma<F32, 2>), grid, dim3(256), lds, s, (float2*)Q, (const float2*)AP,
                                beta, N, Vh, halt);
+        return hipGetLastError();
+    }
+    if ((kernel == 0 || kernel == 1) && partials == nullptr && N > 32 && N <= 64 && prec == Prec::FP32) {
+        const long groups = ((long)((Vh + 15) / 16) * 3 + 3) / 4;
+        const dim3 grid((unsigned)(groups < 2048 ? groups : 2048));
+        hipLaunchKernelGGL(k_pass_a_mfma32, grid, dim3(256), (size_t)64 * 64 * sizeof(float2), s, (float2*)Q,
+                           (const float2*)AP, beta, N, Vh, halt);
         return hipGetLastError();
     }
     switch (prec) {
@@ -1227,6 +1302,150 @@ k_pass_b_mfma(double2* __restrict__ X, const typename S::pair* __restrict__ Qt,
     }
 }
 
+// Pass B on the matrix cores for FP32 storage and 32 < N <= 64 (NT = 4 column tiles).
+// The layout of k_pass_b_mfma, but the three 64 x 64 coefficient matrices do not fit
+// LDS in FP64 (192 KB), so beta C stays FP64 (64 KB, the X increment in FP64 as in
+// the vector kernels) while S^{-1} and S^H are staged in FP32 (32 KB each) and the
+// Q and P products run on v_mfma_f32_16x16x4f32 (FP32 storage and FP32 arithmetic,
+// as the vector kernels).  128 KB of LDS: one workgroup of NW waves per CU, persistent.
+// Accumulator element m of lane l of the FP32 instruction holds row
+// F32_ACC_ROW(m, l) of its 16 x 16 tile (checked on the device by an in-bounds probe).
+#define F32_ACC_ROW(m, l) (4 * ((l) >> 4) + (m))
+template <int NW>
+__global__ void __launch_bounds__(64 * NW)
+k_pass_b_mfma32(double2* __restrict__ X, const float2* __restrict__ Qt, const float2* __restrict__ P,
+                float2* __restrict__ Qn, float2* __restrict__ Pn, const double2* __restrict__ betaC,
+                const double2* __restrict__ Sinv, const double2* __restrict__ SH, int N, int Vh,
+                const SolveState* __restrict__ stt) {
+    constexpr int NT = 4, NQ = 16, NP = 64;
+    typedef float fvec4 __attribute__((ext_vector_type(4)));
+    extern __shared__ double2 cf64[];                                  // [NP][NP] beta C
+    float2* cf32 = reinterpret_cast<float2*>(cf64 + NP * NP);          // [2][NP][NP] S^{-1}, S^H
+    const int mode = stt->pb_mode;
+    if (mode == PB_SKIP) return;
+    const bool full = (mode == PB_FULL);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r16 = lane & 15, k4 = lane >> 4;
+    for (int e = threadIdx.x; e < NP * NP; e += 64 * NW) {
+        const int l = e / NP, j = e % NP;
+        const bool in = l < N && j < N;
+        cf64[e] = in ? betaC[l * MAXN + j] : make_double2(0.0, 0.0);
+        const double2 a = in ? Sinv[l * MAXN + j] : make_double2(0.0, 0.0);
+        const double2 b = in ? SH[l * MAXN + j] : make_double2(0.0, 0.0);
+        cf32[e] = make_float2((float)a.x, (float)a.y);
+        cf32[NP * NP + e] = make_float2((float)b.x, (float)b.y);
+    }
+    __syncthreads();
+    const long nrb = (long)((Vh + 15) / 16) * 3;
+    const long ngroups = (nrb + NW - 1) / NW;
+    for (long g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const long rb0 = g * NW + w;
+        const bool rb_ok = rb0 < nrb;
+        const long rb = rb_ok ? rb0 : nrb - 1;
+        const int c = (int)(rb % 3);
+        const int site = (int)(rb / 3) * 16 + r16;
+        const bool live = rb_ok && site < Vh;
+        const int si = site < Vh ? site : Vh - 1;
+        float pr[NQ], pi[NQ], qr[NQ], qi[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int l = 4 * q + k4;
+            const bool ok = l < N;
+            const int lc = ok ? l : N - 1;
+            const float2 a = P[((long)lc * 3 + c) * Vh + si];
+            const float2 b = Qt[((long)lc * 3 + c) * Vh + si];
+            pr[q] = ok ? a.x : 0.0f;
+            pi[q] = ok ? a.y : 0.0f;
+            qr[q] = ok ? b.x : 0.0f;
+            qi[q] = ok ? b.y : 0.0f;
+        }
+#pragma unroll 1
+        for (int jt = 0; jt < NT; ++jt) {
+            if (jt * 16 >= N) break;
+            const int jo = jt * 16 + r16;  // coefficient column of this lane (A-operand row)
+            dvec4 xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0};
+            fvec4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};  // Qt S^{-1}
+            fvec4 br = {0, 0, 0, 0}, bi = {0, 0, 0, 0};  // P S^H
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int l = 4 * q + k4;
+                const double2 m1 = cf64[l * NP + jo];
+                const bool uq = full && q <= 4 * jt + 3;
+                const bool up = full && q >= 4 * jt;
+                const double dpr = (double)pr[q], dpi = (double)pi[q];
+                xr = __builtin_amdgcn_mfma_f64_16x16x4f64(m1.x, dpr, xr, 0, 0, 0);
+                xi = __builtin_amdgcn_mfma_f64_16x16x4f64(m1.x, dpi, xi, 0, 0, 0);
+                if (uq) {
+                    const float2 m2 = cf32[l * NP + jo];
+                    ar = __builtin_amdgcn_mfma_f32_16x16x4f32(m2.x, qr[q], ar, 0, 0, 0);
+                    ai = __builtin_amdgcn_mfma_f32_16x16x4f32(m2.x, qi[q], ai, 0, 0, 0);
+                    ar = __builtin_amdgcn_mfma_f32_16x16x4f32(-m2.y, qi[q], ar, 0, 0, 0);
+                    ai = __builtin_amdgcn_mfma_f32_16x16x4f32(m2.y, qr[q], ai, 0, 0, 0);
+                }
+                if (up) {
+                    const float2 m3 = cf32[NP * NP + l * NP + jo];
+                    br = __builtin_amdgcn_mfma_f32_16x16x4f32(m3.x, pr[q], br, 0, 0, 0);
+                    bi = __builtin_amdgcn_mfma_f32_16x16x4f32(m3.x, pi[q], bi, 0, 0, 0);
+                    br = __builtin_amdgcn_mfma_f32_16x16x4f32(-m3.y, pi[q], br, 0, 0, 0);
+                    bi = __builtin_amdgcn_mfma_f32_16x16x4f32(m3.y, pr[q], bi, 0, 0, 0);
+                }
+                xr = __builtin_amdgcn_mfma_f64_16x16x4f64(-m1.y, dpi, xr, 0, 0, 0);
+                xi = __builtin_amdgcn_mfma_f64_16x16x4f64(m1.y, dpr, xi, 0, 0, 0);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                // FP64 accumulator m of lane l: output column 4m + l/16 of the tile
+                const int j = jt * 16 + 4 * m + k4;
+                if (live && j < N) {
+                    const long o = ((long)j * 3 + c) * Vh + site;
+                    double2 xv = X[o];
+                    xv.x += xr[m];
+                    xv.y += xi[m];
+                    X[o] = xv;
+                }
+            }
+            if (full) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int j = jt * 16 + F32_ACC_ROW(m, lane);
+                    if (live && j < N) {
+                        const long o = ((long)j * 3 + c) * Vh + site;
+                        const float2 qv = make_float2(ar[m], ai[m]);
+                        Qn[o] = qv;
+                        Pn[o] = make_float2(qv.x + br[m], qv.y + bi[m]);   // P = Q + P S^H
+                    }
+                }
+            }
+        }
+    }
+}
+#undef F32_ACC_ROW
+
+static bool pass_b_mfma32_ok(Prec prec, int N, bool fused) {
+    return !fused && N > 32 && N <= 64 && prec == Prec::FP32;
+}
+
+static void pass_b_mfma32_go(double2* X, const void* Qt, const void* P, void* Qn, void* Pn, const double2* betaC,
+                             const double2* Sinv, const double2* SH, int N, int Vh, const SolveState* st,
+                             hipStream_t s) {
+    // eight waves share the one workgroup per CU that the 128 KB of LDS allows (two
+    // per SIMD, 254 VGPRs each): 1.49x faster than four waves at N = 64 on 32^3 x 64
+    constexpr int NW = 8;
+    const long nrb = (long)((Vh + 15) / 16) * 3;
+    const long groups = (nrb + NW - 1) / NW;
+    const dim3 grid((unsigned)(groups < 256 ? groups : 256));
+    const size_t lds = (size_t)64 * 64 * sizeof(double2) + (size_t)2 * 64 * 64 * sizeof(float2);
+    static bool attr = false;
+    if (!attr) {
+        // a failure here makes the launch below fail, which the caller sees
+        attr = hipFuncSetAttribute((const void*)k_pass_b_mfma32<NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds) == hipSuccess;
+    }
+    hipLaunchKernelGGL(k_pass_b_mfma32<NW>, grid, dim3(64 * NW), lds, s, X, (const float2*)Qt, (const float2*)P,
+                       (float2*)Qn, (float2*)Pn, betaC, Sinv, SH, N, Vh, st);
+}
+
 // matrix-core pass B applies (FP32 / FP64 storage, no fused Gram, 16 < N <= 32:
 // all three coefficient matrices fit in LDS; measured 1.4x faster than the vector
 // kernel at N = 32 on 32^3 x 64, while at N = 64 the per-tile staging makes it slower)
@@ -1262,6 +1481,10 @@ hipError_t launch_pass_b(Prec prec, double2* X, const void* Qt, const void* P, v
     if ((kernel == 0 || kernel == 1) && pass_b_mfma_ok(prec, N, partials != nullptr)) {
         if (prec == Prec::FP64) pass_b_mfma_t<F64>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, s);
         else pass_b_mfma_t<F32>(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, s);
+        return hipGetLastError();
+    }
+    if ((kernel == 0 || kernel == 1) && pass_b_mfma32_ok(prec, N, partials != nullptr)) {
+        pass_b_mfma32_go(X, Qt, P, Qn, Pn, betaC, Sinv, SH, N, Vh, state, s);
         return hipGetLastError();
     }
     switch (prec) {

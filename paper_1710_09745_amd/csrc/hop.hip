@@ -104,7 +104,7 @@ hipError_t links_from64(Prec pd, const void* W64, void* Wd, int nl, long Vh, hip
     return hipGetLastError();
 }
 
-HopShape hop_shape(Prec p, int N, int tr, int tpb, int pf, int kernel, const Geom& g, bool fused) {
+HopShape hop_shape(Prec p, int N, int tr, int tpb, int pf, int kernel, const Geom& g, bool fused, int sched) {
     HopShape h;
     // default kernel: the site-parallel kernel when its grid fills the chip four
     // times over, the lane-split kernel on smaller lattices (measured on MI355X:
@@ -137,6 +137,15 @@ HopShape hop_shape(Prec p, int N, int tr, int tpb, int pf, int kernel, const Geo
     else if (pf == 2) h.pf = 0;
     if (N > 1 && (tr == 1 || tr == 2 || tr == 4 || tr == 8)) h.tr = tr;
     if (N > 1 && (tpb == 1 || tpb == 2 || tpb == 4)) h.tpb = tpb;
+    // per-XCD task queues (not with the fused Gram epilogue, whose per-workgroup
+    // partials must not depend on which workgroup did which task)
+    h.queue_wpc = 0;
+    if (!fused) {
+        if (sched == 2) h.queue_wpc = 1;
+        else if (sched == 3) h.queue_wpc = 2;
+        else if (sched == 4) h.queue_wpc = 4;
+        else if (sched == 5) h.queue_wpc = 8;
+    }
     return h;
 }
 
@@ -158,38 +167,59 @@ int hop_grid(const Geom& g, const HopShape& h, bool fused) {
 template <typename S>
 void launch_hop_s(int nl, const void* W, const void* in, void* out, const void* ctr, double m2, int N,
                   const Geom& g, int out_parity, int epi, const HopShape& h, const int* halt, double* dot,
-                  double2* partials, hipStream_t s);
+                  double2* partials, int* queue, hipStream_t s);
 extern template void launch_hop_s<F64>(int, const void*, const void*, void*, const void*, double, int, const Geom&,
-                                       int, int, const HopShape&, const int*, double*, double2*, hipStream_t);
+                                       int, int, const HopShape&, const int*, double*, double2*, int*, hipStream_t);
 extern template void launch_hop_s<F32>(int, const void*, const void*, void*, const void*, double, int, const Geom&,
-                                       int, int, const HopShape&, const int*, double*, double2*, hipStream_t);
+                                       int, int, const HopShape&, const int*, double*, double2*, int*, hipStream_t);
 extern template void launch_hop_s<H16>(int, const void*, const void*, void*, const void*, double, int, const Geom&,
-                                       int, int, const HopShape&, const int*, double*, double2*, hipStream_t);
+                                       int, int, const HopShape&, const int*, double*, double2*, int*, hipStream_t);
 extern template void launch_hop_s<B16>(int, const void*, const void*, void*, const void*, double, int, const Geom&,
-                                       int, int, const HopShape&, const int*, double*, double2*, hipStream_t);
+                                       int, int, const HopShape&, const int*, double*, double2*, int*, hipStream_t);
 extern template void launch_hop_s<X16>(int, const void*, const void*, void*, const void*, double, int, const Geom&,
-                                       int, int, const HopShape&, const int*, double*, double2*, hipStream_t);
+                                       int, int, const HopShape&, const int*, double*, double2*, int*, hipStream_t);
 
 int hop_dot_blocks(const Geom& g) { return (g.Vh + 63) / 64; }  // lane-split kernel, N = 1
 
+HopQueue hop_queue_layout(const Geom& g, int spb, int* ctr) {
+    HopQueue q{};
+    if (ctr == nullptr || !g.slab) return q;
+    const int nsb = (g.Vh + spb - 1) / spb;
+    const int slice = g.L[0] * g.L[1] * g.L[2] / 2;
+    int bpc = 0;
+    if (slice % spb == 0) {
+        const int bps = slice / spb;
+        for (int Q : {4, 2, 1})
+            if (bps % Q == 0) {
+                bpc = bps / Q;
+                break;
+            }
+    }
+    if (bpc == 0 || nsb % bpc != 0) bpc = 1;
+    q.ctr = ctr;
+    q.bpc = bpc;
+    q.ncell = nsb / bpc;
+    return q;
+}
+
 hipError_t launch_hop(Prec prec, int nl, const void* W, const void* in, void* out, const void* ctr,
                       double m2, int N, const Geom& g, int out_parity, int epi, const HopShape& h,
-                      const int* halt, double* dot, double2* partials, hipStream_t s) {
+                      const int* halt, double* dot, double2* partials, int* queue, hipStream_t s) {
     if (epi == EPI_MASS_DOT_ && (N != 1 || h.tr != 1 || !h.split)) return hipErrorInvalidValue;
     if (h.split && (double)nl * 9.0 * (double)g.Vh * pd_bytes(prec) >= 4294967296.0) {
         // links beyond 32-bit lane offsets: the site-parallel kernel re-bases per matrix
         if (epi == EPI_MASS_DOT_) return hipErrorInvalidValue;
         HopShape h2 = hop_shape(prec, N, 0, 0, 0, 2, g, false);
-        return launch_hop(prec, nl, W, in, out, ctr, m2, N, g, out_parity, epi, h2, halt, dot, partials, s);
+        return launch_hop(prec, nl, W, in, out, ctr, m2, N, g, out_parity, epi, h2, halt, dot, partials, queue, s);
     }
     if (partials != nullptr && (epi != EPI_PLAIN_ || h.split || hop_tile_bytes(prec, N, h) == 0))
         return hipErrorInvalidValue;
     switch (prec) {
-        case Prec::FP64: launch_hop_s<F64>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s); break;
-        case Prec::FP32: launch_hop_s<F32>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s); break;
-        case Prec::FP16: launch_hop_s<H16>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s); break;
-        case Prec::BF16: launch_hop_s<B16>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s); break;
-        case Prec::FX16: launch_hop_s<X16>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s); break;
+        case Prec::FP64: launch_hop_s<F64>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, queue, s); break;
+        case Prec::FP32: launch_hop_s<F32>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, queue, s); break;
+        case Prec::FP16: launch_hop_s<H16>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, queue, s); break;
+        case Prec::BF16: launch_hop_s<B16>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, queue, s); break;
+        case Prec::FX16: launch_hop_s<X16>(nl, W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, queue, s); break;
     }
     return hipGetLastError();
 }

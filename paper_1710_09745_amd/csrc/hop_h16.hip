@@ -3,5 +3,6 @@
 
 namespace bcg {
 template void launch_hop_s<H16>(int, const void*, const void*, void*, const void*, double, int, const Geom&, int,
-                                int, const HopShape&, const int*, double*, double2*, hipStream_t);
+                                int, const HopShape&, const int*, double*, double2*, int*,
+                                hipStream_t);
 }  // namespace bcg

@@ -19,6 +19,31 @@ template <typename S, int TR> struct HopOperands {
     C2<typename S::real> v[TR][3];
 };
 
+// Per-XCD task queues of the site-parallel hop.  The site blocks are grouped into
+// cells of bpc consecutive blocks (a quarter of a time slice where it divides), and
+// cell c belongs to queue c mod 8, so at any moment the eight XCDs work on eight
+// neighbouring cells and the workgroups of one XCD on consecutive blocks of one
+// cell: the x, y and z neighbours of a cell then stay in that XCD's L2 and the
+// t neighbours are the cells the XCDs read a few steps earlier or later.  Queue q
+// holds, for each tile group in turn, the blocks of its cells in order.
+__device__ __forceinline__ int hop_queue_cells(const HopQueue& q, int qq) {
+    return qq < q.ncell ? (q.ncell - 1 - qq) / 8 + 1 : 0;
+}
+__device__ __forceinline__ int hop_queue_tasks(const HopQueue& q, int qq, int ntg) {
+    return hop_queue_cells(q, qq) * q.bpc * ntg;
+}
+// task (tile group tg, site block sb) as tg * nsb + sb for entry li of queue qq
+__device__ __forceinline__ int hop_queue_task(const HopQueue& q, int qq, int li, int ntg) {
+    const int per_tg = hop_queue_cells(q, qq) * q.bpc;
+    const int tg = li / per_tg;
+    const int r = li - tg * per_tg;
+    const int k = r / q.bpc;
+    const int cell = qq + 8 * k;
+    const int sb = cell * q.bpc + (r - k * q.bpc);
+    (void)ntg;
+    return tg * (q.ncell * q.bpc) + sb;
+}
+
 // Issue every load of hop k of direction mu (all independent, so the wave has
 // 9 + 3 TR loads in flight before its first FMA).  Returns nothing; the
 // neighbour index is formed from the site's coordinate along mu with the
@@ -77,7 +102,7 @@ k_hop(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
       typename S::pair* __restrict__ out, float* __restrict__ outs,
       const typename S::pair* __restrict__ ctr, const float* __restrict__ ctrs,
       double m2d, int N, Geom g, int out_parity, int spb, int ntg, const int* __restrict__ halt,
-      double* __restrict__ dot, double2* __restrict__ partials) {
+      double* __restrict__ dot, double2* __restrict__ partials, HopQueue q) {
     using R = typename S::real;
     using E = typename TileElem<S>::type;
     constexpr int NJ = NL / 4;  // hops per direction
@@ -101,9 +126,39 @@ k_hop(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
     }
     const int bps = blocks_per_slice(g, spb);
     const int gcols = tpb * TR;  // columns of one tile group
-    for (int it = blockIdx.x; it < nsb * ntg; it += gridDim.x) {
+    // task order: with a queue, the workgroups of each XCD take the cells of their own
+    // queue in order (then help drain the others); otherwise a static grid-stride walk
+    __shared__ int s_task;
+    const int xcd = (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & 7u);  // XCC_ID, bits 3:0
+    int qi = 0;                                                               // queues visited
+    auto next_task = [&](int prev) -> int {
+        if (q.ctr == nullptr) return prev < 0 ? (int)blockIdx.x : prev + (int)gridDim.x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = -1;
+            while (qi < 8) {
+                const int qq = (xcd + qi) & 7;
+                const int n = hop_queue_tasks(q, qq, ntg);
+                const int li = atomicAdd(&q.ctr[qq], 1);
+                if (li < n) {
+                    t = hop_queue_task(q, qq, li, ntg);
+                    break;
+                }
+                ++qi;
+            }
+            s_task = t;
+        }
+        __syncthreads();
+        return s_task;
+    };
+    for (int it = next_task(-1); it >= 0 && it < nsb * ntg; it = next_task(it)) {
         int sb, tg;
-        xcd_task_tm(it, nsb, ntg, bps, sb, tg);
+        if (q.ctr != nullptr) {
+            tg = it / nsb;
+            sb = it - tg * nsb;
+        } else {
+            xcd_task_tm(it, nsb, ntg, bps, sb, tg);
+        }
         const int cend = (ntg == 1) ? N : min(N, (tg + 1) * gcols);
         const int i0 = sb * spb + lane_site;
         const bool live = i0 < g.Vh;
@@ -190,6 +245,14 @@ k_hop(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mydot;
         __syncthreads();
         if (threadIdx.x == 0) dot[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    }
+    if (q.ctr != nullptr && threadIdx.x == 0) {
+        // every workgroup has drained all eight queues when it gets here; the last one
+        // to arrive resets the counters for the next launch
+        __threadfence();
+        if (atomicAdd(&q.ctr[8], 1) == (int)gridDim.x - 1) {
+            for (int i = 0; i < 9; ++i) atomicExch(&q.ctr[i], 0);
+        }
     }
 }
 
@@ -334,7 +397,7 @@ k_hop_ls(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
 template <typename S, int TR, int NL, bool PF, int NB, bool GR>
 static void launch_hop_g(const void* W, const void* in, void* out, const void* ctr, double m2, int N,
                          const Geom& g, int out_parity, int epi, const HopShape& h, const int* halt,
-                         double* dot, double2* partials, hipStream_t s) {
+                         double* dot, double2* partials, int* queue, hipStream_t s) {
     using P = typename S::pair;
     const long Vh = g.Vh;
     auto scale = [&](const void* p, long cols, int K) -> float* {
@@ -348,10 +411,18 @@ static void launch_hop_g(const void* W, const void* in, void* out, const void* c
     float* ins = scale(in, N, 3);
     float* outs = scale(out, N, 3);
     float* ctrs = scale(ctr, N, 3);
+    HopQueue q{};
+    if (!GR && queue != nullptr && h.queue_wpc > 0) {
+        q = hop_queue_layout(g, spb, queue);
+        if (q.ctr != nullptr) {
+            const unsigned pg = 256u * (unsigned)h.queue_wpc;
+            if (pg < grid.x) grid.x = pg;
+        }
+    }
 #define HOP_GO(E)                                                                                      \
     hipLaunchKernelGGL((k_hop<S, TR, NL, E, PF, NB, GR>), grid, dim3(256), lds, s, (const P*)W, Ws,        \
                        (const P*)in, ins, (P*)out, outs, (const P*)ctr, ctrs, m2, N, g, out_parity, spb, \
-                       ntg, halt, dot, partials)
+                       ntg, halt, dot, partials, q)
     if (epi == EPI_PLAIN) HOP_GO(EPI_PLAIN);
     else if constexpr (!GR) {
         if (epi == EPI_MASS) HOP_GO(EPI_MASS);
@@ -363,8 +434,8 @@ static void launch_hop_g(const void* W, const void* in, void* out, const void* c
 template <typename S, int TR, int NL, bool PF>
 static void launch_hop_t(const void* W, const void* in, void* out, const void* ctr, double m2,
                          int N, const Geom& g, int out_parity, int epi, const HopShape& h,
-                         const int* halt, double* dot, double2* partials, hipStream_t s) {
-#define HG(NBV, GRV) launch_hop_g<S, TR, NL, PF, NBV, GRV>(W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s)
+                         const int* halt, double* dot, double2* partials, int* queue, hipStream_t s) {
+#define HG(NBV, GRV) launch_hop_g<S, TR, NL, PF, NBV, GRV>(W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, queue, s)
     if (partials == nullptr) return HG(1, false);
     switch (pad_n(N)) {
         case 1: return HG(1, true);
@@ -407,7 +478,7 @@ static void launch_hop_ls(const void* W, const void* in, void* out, const void* 
 template <typename S, int NL>
 static void launch_hop_nl(const void* W, const void* in, void* out, const void* ctr, double m2,
                           int N, const Geom& g, int out_parity, int epi, const HopShape& h,
-                          const int* halt, double* dot, double2* partials, hipStream_t s) {
+                          const int* halt, double* dot, double2* partials, int* queue, hipStream_t s) {
     if (h.split) {
 #define HOP_DT(T)                                                                                        \
     (h.pf ? launch_hop_ls<S, T, NL, true>(W, in, out, ctr, m2, N, g, out_parity, epi, halt, dot, s)      \
@@ -422,8 +493,8 @@ static void launch_hop_nl(const void* W, const void* in, void* out, const void* 
         return;
     }
 #define HOP_TR(T)                                                                                          \
-    (h.pf ? launch_hop_t<S, T, NL, true>(W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s) \
-          : launch_hop_t<S, T, NL, false>(W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s))
+    (h.pf ? launch_hop_t<S, T, NL, true>(W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, queue, s) \
+          : launch_hop_t<S, T, NL, false>(W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, queue, s))
     switch (h.tr) {
         case 1: HOP_TR(1); break;
         case 2: HOP_TR(2); break;
@@ -436,9 +507,9 @@ static void launch_hop_nl(const void* W, const void* in, void* out, const void* 
 template <typename S>
 void launch_hop_s(int nl, const void* W, const void* in, void* out, const void* ctr, double m2,
                          int N, const Geom& g, int out_parity, int epi, const HopShape& h,
-                         const int* halt, double* dot, double2* partials, hipStream_t s) {
-    if (nl == 16) launch_hop_nl<S, 16>(W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s);
-    else launch_hop_nl<S, 8>(W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, s);
+                         const int* halt, double* dot, double2* partials, int* queue, hipStream_t s) {
+    if (nl == 16) launch_hop_nl<S, 16>(W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, queue, s);
+    else launch_hop_nl<S, 8>(W, in, out, ctr, m2, N, g, out_parity, epi, h, halt, dot, partials, queue, s);
 }
 
 }  // namespace bcg

@@ -18,6 +18,15 @@ struct HopShape {
     int tpb;    // site-parallel kernel: lane groups per workgroup sharing the same sites
     int pf;     // 1: two folded matrices in flight per loop trip
     int split;  // 1: direction-split kernel (four waves share 64 sites), 0: site-parallel
+    int queue_wpc = 0;  // site-parallel kernel: > 0 = per-XCD task queues, this many workgroups per CU
+};
+
+// Per-XCD task queues of the site-parallel hop: ctr[0..7] queue counters, ctr[8] the
+// count of finished workgroups (all reset to 0 by the last one); cells of bpc site blocks
+struct HopQueue {
+    int* ctr;
+    int ncell;
+    int bpc;
 };
 
 // bytes per stored complex number, and bytes of a [cols][K][Vh] allocation
@@ -52,14 +61,18 @@ hipError_t links_from64(Prec pd, const void* W64, void* Wd, int nl, long Vh, hip
 // nonzero tr, tpb override the defaults, pf: 1 on, 2 off; kernel: 1 lane split,
 // 2 site-parallel, 0 chosen by lattice size; fused (Gram epilogue) always takes
 // the site-parallel kernel
-HopShape hop_shape(Prec p, int N, int tr, int tpb, int pf, int kernel, const Geom& g, bool fused);
+// sched: 0 default, 1 static slab order, 2..5 per-XCD queues with 1, 2, 4, 8 workgroups per CU
+HopShape hop_shape(Prec p, int N, int tr, int tpb, int pf, int kernel, const Geom& g, bool fused, int sched = 0);
 // partial dot products written by the EPI_MASS_DOT hop (one right-hand side)
 int hop_dot_blocks(const Geom& g);
 // partials != nullptr (EPI_PLAIN only): also T^H T partials of the output, one per
 // workgroup of the persistent grid hop_grid(g, h, true)
+// queue: 9 zero-initialised ints of the context (per-XCD task queues), or nullptr
 hipError_t launch_hop(Prec prec, int nl, const void* W, const void* in, void* out, const void* ctr,
                       double m2, int N, const Geom& g, int out_parity, int epi, const HopShape& h,
-                      const int* halt, double* dot, double2* partials, hipStream_t s);
+                      const int* halt, double* dot, double2* partials, int* queue, hipStream_t s);
+// cells of the per-XCD queues for spb-site blocks (ctr == nullptr in the result: no queue)
+HopQueue hop_queue_layout(const Geom& g, int spb, int* ctr);
 size_t hop_tile_bytes(Prec prec, int N, const HopShape& h);
 int hop_grid(const Geom& g, const HopShape& h, bool fused);
 enum { EPI_PLAIN_ = 0, EPI_MASS_ = 1, EPI_MASS_DOT_ = 2 };

@@ -130,3 +130,34 @@ def config_inputs(config: int, dims=None, nrhs=None):
         lng = None
     b = rhs(make_rng(seed_for(config, 1)), nrhs, dims)
     return fat, lng, b
+
+
+def diluted_noise_sources(dims, n_sources: int, n_subsets: int, rng: np.random.Generator) -> np.ndarray:
+    """Stochastic-trace sources split into disjoint-support pieces, as in the
+    paper's measurement workload (Sec. 7.1: 24 noise sources, each partitioned
+    into 8 disjoint subsets): n_sources fields on the even checkerboard with
+    complex Z4 noise (1, i, -1, -i) in every colour component, each split into
+    n_subsets pieces by the site's corner of the 2^3 spatial unit cube,
+    (x mod 2) + 2 (y mod 2) + 4 (z mod 2) (n_subsets = 8; with fewer, that index
+    mod n_subsets).  Returns [n_sources * n_subsets][V/2][3], piece s of source k
+    at k * n_subsets + s."""
+    check_dims(dims)
+    Lx, Ly, Lz, Lt = (int(d) for d in dims)
+    vh = volume(dims) // 2
+    lex = np.arange(volume(dims))
+    x = lex % Lx
+    y = (lex // Lx) % Ly
+    z = (lex // (Lx * Ly)) % Lz
+    t = lex // (Lx * Ly * Lz)
+    even = ((x + y + z + t) % 2) == 0
+    cb = lex[even] >> 1
+    corner = ((x[even] & 1) + 2 * (y[even] & 1) + 4 * (z[even] & 1)) % n_subsets
+    cls = np.empty(vh, dtype=np.int64)
+    cls[cb] = corner
+    noise = np.exp(0.5j * np.pi * rng.integers(0, 4, size=(n_sources, vh, 3)))
+    out = np.zeros((n_sources * n_subsets, vh, 3), dtype=np.complex128)
+    for k in range(n_sources):
+        for s in range(n_subsets):
+            sel = cls == s
+            out[k * n_subsets + s, sel] = noise[k, sel]
+    return out

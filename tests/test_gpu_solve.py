@@ -357,10 +357,11 @@ def test_gram_kernels_match_oracle(n):
         assert true_rel_res(op, B, X.cpu().numpy()).max() <= 1e-8
 
 
-@pytest.mark.parametrize("n,threads", [(4, 64), (16, 64), (16, 1024), (32, 256), (64, 1024)])
+@pytest.mark.parametrize("n,threads", [(4, 64), (16, 64), (16, 1024), (32, 256), (64, 1024), (1, 0), (7, 0)])
 def test_small_kernel_threads_match_oracle(n, threads):
     """The one-workgroup N x N kernels give the same iterates with one, four or
-    sixteen waves (a request that would exceed four entries per thread falls back)."""
+    sixteen waves (a request that would exceed four entries per thread falls back;
+    threads = 0 is the default choice by N)."""
     dims = (6, 6, 6, 8)
     fat, lng, B = inputs(dims, True, n, 7100 + n)
     m = 0.15
