@@ -8,7 +8,7 @@
 // while the others go on.  FP64 storage, block vectors [N][3][Vh] pairs.
 //
 // Reductions are deterministic: one partial per (column, workgroup), summed in
-// a fixed order by a single-workgroup kernel.
+// a fixed order by a single-workgroup kernel (16 lanes per column).
 #include "device_common.h"
 #include "internal.h"
 
@@ -48,13 +48,25 @@ k_pb_dot(const double2* __restrict__ P, const double2* __restrict__ AP, int Vh, 
     if (threadIdx.x == 0) partials[(long)j * gridDim.x + blockIdx.x] = s;
 }
 
+// sum over b of partials[j][b] for column j = threadIdx.x / 16, in a fixed order: lane
+// g of the column's 16 takes b = g, g + 16, ..., then an xor butterfly over the 16 lanes
+// (1024 threads: up to 64 columns); every lane of the group ends with the total
+__device__ double pb_column_sum(const double* __restrict__ partials, int nb, int N) {
+    const int j = threadIdx.x >> 4, g = threadIdx.x & 15;
+    double v = 0.0;
+    if (j < N)
+        for (int b = g; b < nb; b += 16) v += partials[(long)j * nb + b];
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
+    return v;
+}
+
 // alpha_j = rr_j / p_j^H A p_j for the active columns (0 for the others)
-__global__ void k_pb_alpha(const double* __restrict__ partials, int nb, int N, PbState* st) {
+__global__ void __launch_bounds__(1024) k_pb_alpha(const double* __restrict__ partials, int nb, int N, PbState* st) {
     if (st->halt) return;
-    const int j = threadIdx.x;
-    if (j < N) {
-        double pap = 0.0;
-        for (int b = 0; b < nb; ++b) pap += partials[(long)j * nb + b];
+    const int j = threadIdx.x >> 4;
+    const double pap = pb_column_sum(partials, nb, N);
+    if (j < N && (threadIdx.x & 15) == 0) {
         double a = 0.0;
         if (st->active[j]) {
             if (!(pap > 0.0)) {
@@ -98,15 +110,14 @@ k_pb_update1(double2* __restrict__ X, double2* __restrict__ R, const double2* __
 }
 
 // beta_j, the iterated residuals and the convergence of each column
-__global__ void k_pb_beta(const double* __restrict__ partials, int nb, int N, PbState* st) {
+__global__ void __launch_bounds__(1024) k_pb_beta(const double* __restrict__ partials, int nb, int N, PbState* st) {
     if (st->halt) return;
     __shared__ int still;
     if (threadIdx.x == 0) still = 0;
     __syncthreads();
-    const int j = threadIdx.x;
-    if (j < N && st->active[j]) {
-        double rr = 0.0;
-        for (int b = 0; b < nb; ++b) rr += partials[(long)j * nb + b];
+    const int j = threadIdx.x >> 4;
+    const double rr = pb_column_sum(partials, nb, N);
+    if (j < N && (threadIdx.x & 15) == 0 && st->active[j]) {
         st->beta[j] = rr / st->rr[j];
         st->rr[j] = rr;
         st->relres[j] = sqrt(rr) / st->bnorm[j];
@@ -179,7 +190,7 @@ hipError_t launch_pb_dot(const double2* P, const double2* AP, int N, int Vh, dou
     return hipGetLastError();
 }
 hipError_t launch_pb_alpha(const double* partials, int N, int Vh, PbState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_pb_alpha, dim3(1), dim3(64), 0, s, partials, pb_blocks(Vh), N, st);
+    hipLaunchKernelGGL(k_pb_alpha, dim3(1), dim3(1024), 0, s, partials, pb_blocks(Vh), N, st);
     return hipGetLastError();
 }
 hipError_t launch_pb_update1(double2* X, double2* R, const double2* P, const double2* AP, int N, int Vh,
@@ -188,7 +199,7 @@ hipError_t launch_pb_update1(double2* X, double2* R, const double2* P, const dou
     return hipGetLastError();
 }
 hipError_t launch_pb_beta(const double* partials, int N, int Vh, PbState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_pb_beta, dim3(1), dim3(64), 0, s, partials, pb_blocks(Vh), N, st);
+    hipLaunchKernelGGL(k_pb_beta, dim3(1), dim3(1024), 0, s, partials, pb_blocks(Vh), N, st);
     return hipGetLastError();
 }
 hipError_t launch_pb_update2(double2* P, const double2* R, int N, int Vh, const PbState* st, hipStream_t s) {

@@ -11,7 +11,10 @@
   (C^H H C)_ii equal the true residual norms;
 * a reliable update is a no-op in exact arithmetic: with FP64 "sloppy"
   storage the iteration count and solution match the plain solve;
-* breakdown on linearly dependent columns, error on a zero column.
+* breakdown on linearly dependent columns, error on a zero column;
+* the initial-guess branch: from the dense solution it stops at once, from a
+  perturbed guess it reaches the dense solution along the iterates of the shifted
+  residual system.
 """
 import numpy as np
 import pytest
@@ -67,6 +70,34 @@ def test_block_cg_matches_dense_solve(dims, improved, m, n):
     # true residual computed independently from the dense matrix
     res = np.linalg.norm(oracle.to_mat(B) - A @ Xm, axis=0) / np.linalg.norm(oracle.to_mat(B), axis=0)
     assert res.max() <= 1.01e-12
+
+
+def test_initial_guess_branch():
+    """The X0 branch, pinned by the dense solve: started from the exact solution it
+    stops at once and returns it; started from a partial guess it reaches the dense
+    solution, and its iterates are those of the residual system shifted by X0 (the
+    same Krylov space in exact arithmetic)."""
+    op, B = small_problem(n=3, seed=11)
+    A = dense_A(op)
+    Bm = oracle.to_mat(B)
+    Xd = np.linalg.solve(A, Bm)
+    Xe = oracle.from_mat(Xd, op.Vh)
+    X, info = oracle.block_cg_rq(op.apply, B, 1e-10, X0=Xe)
+    assert info.iters == 0 and info.converged
+    assert np.abs(oracle.to_mat(X) - Xd).max() <= 1e-12 * np.abs(Xd).max()
+    r = synth.make_rng(12)
+    G = synth.gaussian_complex(r, Xd.shape) * 0.1 * np.abs(Xd).max()
+    X0 = oracle.from_mat(Xd + G, op.Vh)
+    X, info = oracle.block_cg_rq(op.apply, B, 1e-12, X0=X0)
+    assert info.converged
+    assert np.linalg.norm(oracle.to_mat(X) - Xd) / np.linalg.norm(Xd) <= np.linalg.cond(A) * 1e-12
+    # k iterations from X0 equal X0 plus k iterations on B - A X0 from zero
+    R0 = oracle.from_mat(Bm - A @ oracle.to_mat(X0), op.Vh)
+    for k in (1, 3):
+        Xk, _ = oracle.block_cg_rq(op.apply, B, 1e-30, max_iter=k, X0=X0)
+        Dk, _ = oracle.block_cg_rq(op.apply, R0, 1e-30, max_iter=k)
+        ref = oracle.to_mat(X0) + oracle.to_mat(Dk)
+        assert np.abs(oracle.to_mat(Xk) - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
 def test_config1_block_cg():
