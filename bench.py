@@ -154,6 +154,12 @@ def main():
     ap.add_argument("--tsm-lattice", default="16x16x16x48")
     ap.add_argument("--tsm-mass", type=float, default=0.05)
     ap.add_argument("--tsm-blocks", default="1,8,16,24,32,48,64")
+    ap.add_argument("--tsm-links", choices=["random", "smooth"], default="random",
+                    help="tsm192 links: Gaussian fat + Haar long (random), or smooth SU(3) exp(i eps H) "
+                         "fields standing in for smeared ensembles (smooth)")
+    ap.add_argument("--tsm-eps", type=float, default=0.6, help="eps of the smooth links")
+    ap.add_argument("--tsm-pseudo", action="store_true",
+                    help="tsm192: also run pseudo-block CG at every block size > 1 (FP64 storage)")
     ap.add_argument("--nrhs", type=int, default=16)
     ap.add_argument("--prec", default=None, help="storage precision override (fp64/fp32/fp16/bf16/fix16)")
     ap.add_argument("--no-cg", action="store_true")
@@ -412,8 +418,11 @@ def tsm192(args, bcg, synth, torch):
     m = args.tsm_mass
     prec = args.prec or "fp64"
     blocks = [int(b) for b in args.tsm_blocks.split(",")]
-    fat = synth.fat_links(synth.make_rng(synth.seed_for(6, 0)), dims)
-    lng = synth.long_links(synth.make_rng(synth.seed_for(6, 0) + 1), dims)
+    if args.tsm_links == "smooth":
+        fat, lng = synth.smooth_links(synth.make_rng(synth.seed_for(6, 4)), dims, args.tsm_eps)
+    else:
+        fat = synth.fat_links(synth.make_rng(synth.seed_for(6, 0)), dims)
+        lng = synth.long_links(synth.make_rng(synth.seed_for(6, 0) + 1), dims)
     B = synth.diluted_noise_sources(dims, 24, 8, synth.make_rng(synth.seed_for(6, 1)))
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -422,47 +431,54 @@ def tsm192(args, bcg, synth, torch):
     ctx.set_mass(m)
     Bt = torch.from_numpy(B).to(dev)
     total = Bt.shape[0]
-    rows = []
-    for b in blocks:
-        if total % b:
-            continue
-        row = {"block": b, "solves": total // b}
+
+    def solve_all(kind, b):
+        """Every source solved to 5e-6 and to 2e-9 with one method in blocks of b."""
+        out = {}
         for name, tol in (("sloppy", 5e-6), ("fine", 2e-9)):
             ctx.set_solver(tol=tol, max_iter=100000, prec=prec, ru_delta=0.1)
-            ctx.set_monitor(Progress(f"tsm192 b={b} {name}"))
-            if b == 1:
-                ctx.solve_cg(Bt[:1])          # warm
-            else:
-                ctx.solve(Bt[:b].contiguous(), raise_on_error=False)
+            ctx.set_monitor(Progress(f"tsm192 {kind} b={b} {name}"))
+            call = {"cg": ctx.solve_cg, "block": ctx.solve, "pseudo": ctx.solve_pseudo}[kind]
+            call(Bt[:b].contiguous(), raise_on_error=False)          # warm
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             its = rhs_its = 0
             worst = 0.0
             fails = 0
             for j in range(0, total, b):
-                Bj = Bt[j:j + b].contiguous()
-                if b == 1:
-                    _, info = ctx.solve_cg(Bj, raise_on_error=False)
-                    its += info["iters"]
-                    rhs_its += info["iters"]
-                else:
-                    _, info = ctx.solve(Bj, raise_on_error=False)
-                    its += info["iters"]
-                    rhs_its += info["iters"] * b
+                _, info = call(Bt[j:j + b].contiguous(), raise_on_error=False)
+                its += info["iters"]
+                # block and pseudo-block: one iteration applies A to all b columns; CG runs
+                # its columns in turn and reports their summed iterations
+                rhs_its += info["iters"] if kind == "cg" else info["iters"] * b
                 worst = max(worst, info["max_true_rel_res"])
                 fails += info["rc"] != 0
             torch.cuda.synchronize()
-            row[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 1), "iters": its, "rhs_iters": rhs_its,
+            out[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 1), "iters": its, "rhs_iters": rhs_its,
                          "max_true_rel_res": worst, "failed_solves": fails}
-        row["total_ms"] = round(row["sloppy"]["ms"] + row["fine"]["ms"], 1)
+        out["total_ms"] = round(out["sloppy"]["ms"] + out["fine"]["ms"], 1)
+        return out
+
+    rows = []
+    for b in blocks:
+        if total % b:
+            continue
+        row = {"block": b, "solves": total // b}
+        row.update(solve_all("cg" if b == 1 else "block", b))
+        if b > 1 and args.tsm_pseudo and prec == "fp64":
+            row["pseudo"] = solve_all("pseudo", b)
         rows.append(row)
         print(f"[tsm192] b={b}: {row['total_ms']} ms (sloppy {row['sloppy']['iters']} + fine "
-              f"{row['fine']['iters']} iterations)", file=sys.stderr, flush=True)
+              f"{row['fine']['iters']} iterations)"
+              + (f"; pseudo-block {row['pseudo']['total_ms']} ms" if "pseudo" in row else ""),
+              file=sys.stderr, flush=True)
     base = next((r["total_ms"] for r in rows if r["block"] == 1), None)
     for r in rows:
         r["speedup_vs_cg"] = round(base / r["total_ms"], 3) if base else None
+    links = ("Gaussian fat + Haar long" if args.tsm_links == "random"
+             else f"smooth SU(3) exp(i eps H), eps={args.tsm_eps}")
     print(json.dumps({"metric": "total time for 192 diluted sources, sloppy 5e-6 + fine 2e-9, vs block size",
-                      "lattice": list(dims), "mass": m, "storage": prec, "data": "synthetic",
+                      "lattice": list(dims), "mass": m, "storage": prec, "links": links, "data": "synthetic",
                       "rows": rows}), flush=True)
     ctx.close()
 

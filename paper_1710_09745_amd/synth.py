@@ -15,7 +15,9 @@ Canonical layouts (complex128, C order):
 The workload stands in for the paper's HISQ ensembles (Table 1) and its
 diluted noise sources (Sec. 7.1), which are not available: Haar-random SU(3)
 long links, fat links with iid Gaussian entries of standard deviation 1/3 in
-real and imaginary part, and iid standard-normal complex right-hand sides.
+real and imaginary part, and iid standard-normal complex right-hand sides; for
+the diluted-source workload also smooth SU(3) links (exp(i eps H), closer to
+smeared ensembles).
 """
 from __future__ import annotations
 
@@ -81,6 +83,29 @@ def fat_links(rng: np.random.Generator, dims, scale: float = 1.0 / 3.0) -> np.nd
 def long_links(rng: np.random.Generator, dims) -> np.ndarray:
     """Long (three-hop) links: Haar SU(3)."""
     return haar_su3(rng, (4, volume(dims)))
+
+
+def smooth_su3(rng: np.random.Generator, shape, eps: float) -> np.ndarray:
+    """SU(3) matrices exp(i eps H) with H traceless Hermitian, H = (G + G^H)/2 minus
+    its trace part for a complex Ginibre G (entries of variance 1/2 in Re and Im):
+    eps = 0 is the unit matrix, eps around 0.6 gives an average Re tr U / 3 of about
+    0.8, the range of smeared (fat) links, and large eps approaches Haar."""
+    g = gaussian_complex(rng, tuple(shape) + (3, 3), 1.0 / np.sqrt(2.0))
+    h = 0.5 * (g + np.conj(np.swapaxes(g, -1, -2)))
+    tr = np.trace(h, axis1=-2, axis2=-1) / 3.0
+    h = h - tr[..., None, None] * np.eye(3)
+    w, v = np.linalg.eigh(h)
+    e = np.exp(1j * float(eps) * w)
+    return np.ascontiguousarray((v * e[..., None, :]) @ np.conj(np.swapaxes(v, -1, -2)))
+
+
+def smooth_links(rng: np.random.Generator, dims, eps: float):
+    """Fat and long links as independent smooth SU(3) fields (smooth_su3): a
+    stand-in for the smeared links of a physical ensemble, whose staggered spectrum
+    has the clustered low modes that the Haar / Gaussian links lack."""
+    fat = smooth_su3(rng, (4, volume(dims)), eps)
+    lng = smooth_su3(rng, (4, volume(dims)), eps)
+    return fat, lng
 
 
 def unit_links(dims) -> np.ndarray:

@@ -36,6 +36,15 @@ def col_rel_err(got, ref):
     return d / r
 
 
+def elem_rel_err(got, ref):
+    """Largest elementwise error of each column, relative to that column's largest
+    element: localises a wrong site, colour or column that a norm could average out."""
+    n = ref.shape[0]
+    d = np.abs(got - ref).reshape(n, -1).max(axis=1)
+    r = np.abs(ref).reshape(n, -1).max(axis=1)
+    return d / r
+
+
 def true_rel_res(op: oracle.Operator, B, X):
     n = B.shape[0]
     R = B - op.apply(X)

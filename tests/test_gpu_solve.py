@@ -315,7 +315,8 @@ def test_fused_gram_path_matches_oracle(prec, n):
 
 
 @pytest.mark.parametrize("kernel,tr,tpb,pf,cpt", [(2, 1, 4, 1, 1), (2, 2, 2, 0, 2), (2, 8, 1, 1, 4), (2, 4, 4, 1, 2),
-                                                  (1, 1, 0, 0, 1), (1, 2, 0, 1, 2), (1, 8, 0, 1, 4), (0, 0, 0, 0, 0)])
+                                                  (2, 8, 2, 1, 4), (1, 1, 0, 0, 1), (1, 2, 0, 1, 2), (1, 8, 0, 1, 4),
+                                                  (0, 0, 0, 0, 0)])
 def test_launch_shapes_match_oracle(kernel, tr, tpb, pf, cpt):
     """Both hop kernels (direction split, site-parallel) with every register tile,
     lane-group and pipelining choice, and every pass column tile, give the same

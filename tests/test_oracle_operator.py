@@ -196,3 +196,17 @@ def test_haar_links_are_su3():
     eye = np.eye(3)
     assert np.abs(u @ u.conj().transpose(0, 2, 1) - eye).max() < 1e-13
     assert np.abs(np.linalg.det(u) - 1).max() < 1e-13
+
+
+def test_smooth_links_are_su3_and_interpolate():
+    """smooth_su3: unitary with determinant 1; eps = 0 is the unit matrix; the mean
+    of Re tr U / 3 falls monotonically with eps (about 0.8 at eps = 0.6)."""
+    eye = np.eye(3)
+    for eps in (0.0, 0.6, 2.0):
+        u = synth.smooth_su3(synth.make_rng(72), (400,), eps)
+        assert np.abs(u @ u.conj().transpose(0, 2, 1) - eye).max() < 1e-13
+        assert np.abs(np.linalg.det(u) - 1).max() < 1e-13
+    assert np.abs(synth.smooth_su3(synth.make_rng(73), (10,), 0.0) - eye).max() < 1e-14
+    means = [np.mean(np.real(np.trace(synth.smooth_su3(synth.make_rng(74), (2000,), e), axis1=1, axis2=2))) / 3
+             for e in (0.2, 0.6, 1.2)]
+    assert means[0] > means[1] > means[2] and 0.7 < means[1] < 0.9
