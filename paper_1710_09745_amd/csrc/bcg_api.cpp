@@ -483,17 +483,18 @@ int bcg_create(bcg_ctx** out, const int dims[4], int improved, void* hip_stream)
     }
     if (V >= (1L << 30)) return fail(nullptr, BCG_ERR_ARG, "lattice too large for 32-bit site indices");
     if (improved != 0 && improved != 1) return fail(nullptr, BCG_ERR_ARG, "improved must be 0 or 1");
-    static bool setup = false;
-    if (!setup) {
-        hipError_t e = small_setup();
-        if (e != hipSuccess) return fail(nullptr, BCG_ERR_HIP, std::string("kernel setup: ") + hipGetErrorString(e));
-        setup = true;
-    }
     int dev = 0;
     {
         hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess) return fail(nullptr, BCG_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
         if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(nullptr, BCG_ERR_ARG, "device index out of range");
+        // kernel attributes (dynamic LDS above the default limit), once per device
+        static bool setup[SCRATCH_MAX_DEVICES] = {};
+        if (!setup[dev]) {
+            if ((e = small_setup()) != hipSuccess || (e = blas_setup()) != hipSuccess)
+                return fail(nullptr, BCG_ERR_HIP, std::string("kernel setup: ") + hipGetErrorString(e));
+            setup[dev] = true;
+        }
         if (!g_scratch[dev]) {
             void* p = nullptr;
             e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));

@@ -1422,6 +1422,11 @@ k_pass_b_mfma32(double2* __restrict__ X, const float2* __restrict__ Qt, const fl
 }
 #undef F32_ACC_ROW
 
+// eight waves share the one workgroup per CU that the 128 KB of LDS allows (two per
+// SIMD, 254 VGPRs each): 1.49x faster than four waves at N = 64 on 32^3 x 64
+constexpr int PASS_B32_NW = 8;
+constexpr size_t PASS_B32_LDS = (size_t)64 * 64 * sizeof(double2) + (size_t)2 * 64 * 64 * sizeof(float2);
+
 static bool pass_b_mfma32_ok(Prec prec, int N, bool fused) {
     return !fused && N > 32 && N <= 64 && prec == Prec::FP32;
 }
@@ -1429,21 +1434,17 @@ static bool pass_b_mfma32_ok(Prec prec, int N, bool fused) {
 static void pass_b_mfma32_go(double2* X, const void* Qt, const void* P, void* Qn, void* Pn, const double2* betaC,
                              const double2* Sinv, const double2* SH, int N, int Vh, const SolveState* st,
                              hipStream_t s) {
-    // eight waves share the one workgroup per CU that the 128 KB of LDS allows (two
-    // per SIMD, 254 VGPRs each): 1.49x faster than four waves at N = 64 on 32^3 x 64
-    constexpr int NW = 8;
+    constexpr int NW = PASS_B32_NW;
     const long nrb = (long)((Vh + 15) / 16) * 3;
     const long groups = (nrb + NW - 1) / NW;
     const dim3 grid((unsigned)(groups < 256 ? groups : 256));
-    const size_t lds = (size_t)64 * 64 * sizeof(double2) + (size_t)2 * 64 * 64 * sizeof(float2);
-    static bool attr = false;
-    if (!attr) {
-        // a failure here makes the launch below fail, which the caller sees
-        attr = hipFuncSetAttribute((const void*)k_pass_b_mfma32<NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds) == hipSuccess;
-    }
-    hipLaunchKernelGGL(k_pass_b_mfma32<NW>, grid, dim3(64 * NW), lds, s, X, (const float2*)Qt, (const float2*)P,
-                       (float2*)Qn, (float2*)Pn, betaC, Sinv, SH, N, Vh, st);
+    hipLaunchKernelGGL(k_pass_b_mfma32<PASS_B32_NW>, grid, dim3(64 * NW), PASS_B32_LDS, s, X, (const float2*)Qt,
+                       (const float2*)P, (float2*)Qn, (float2*)Pn, betaC, Sinv, SH, N, Vh, st);
+}
+
+hipError_t blas_setup() {
+    return hipFuncSetAttribute((const void*)k_pass_b_mfma32<PASS_B32_NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)PASS_B32_LDS);
 }
 
 // matrix-core pass B applies (FP32 / FP64 storage, no fused Gram, 16 < N <= 32:

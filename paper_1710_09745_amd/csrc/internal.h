@@ -180,7 +180,11 @@ hipError_t launch_pb_update2(double2* P, const double2* R, int N, int Vh, const 
 hipError_t launch_pb_start(const double* colnorm_partials, int N, int Vh, PbState* st, const int* restart,
                            double tol, int first, hipStream_t s);
 
+// kernel attributes of blas.hip (dynamic LDS above the default limit), for the current device
+hipError_t blas_setup();
+
 // small.hip -------------------------------------------------------------------------------------
+// kernel attributes of small.hip (dynamic LDS above the default limit), for the current device
 hipError_t small_setup();
 // initial thin QR of R from H = R^H R:  C (upper) and Cinv; relres, rho_ru; halts on breakdown
 hipError_t launch_small_init(const double2* H, double2* C, double2* Cinv, SolveState* st, int N,
