@@ -176,7 +176,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU; the multi-GPU path (right-hand-side blocks "
+        print("bench.py: the solver runs on one GPU; the multi-GPU path (right-hand-side blocks "
               "per GPU, or lattice domain decomposition) is a design only. Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)

@@ -473,7 +473,7 @@ template <typename S, int NB> struct FusedTile {
 };
 
 // LDS bytes a fused epilogue of precision prec and block size N would need, or 0
-// when it does not fit the 64 KB budget this build allows per workgroup.
+// when it does not fit the 64 KB LDS budget the fused epilogues keep per workgroup.
 size_t fused_tile_bytes(Prec prec, int N) {
     const int nb = pad_n(N);
     const size_t e = (prec == Prec::FP64) ? 16 : 8;
