@@ -260,9 +260,10 @@ int bcg_set_stability(bcg_ctx *ctx, int ru_window, int stall_limit, int qr_passe
  *                         x-th eighth of every time slice and all XCDs sweep the
  *                         slices together, 2: plain lexicographic order
  *   BCG_OPT_PASS_KERNEL   1: passes A and B on the matrix cores (FP64 MFMA) for
- *                         16 < N <= 32 in FP32 / FP64 storage, and for
- *                         32 < N <= 64 in FP32 storage (FP32 MFMA for the FP32
- *                         products, FP64 MFMA for the X increment), otherwise vector
+ *                         16 < N <= 32 in FP32 / FP64 storage, pass A also for
+ *                         32 < N <= 64 in FP64 storage, and both passes for
+ *                         32 < N <= 64 in FP32 storage with FP32 MFMA for the FP32
+ *                         products (FP64 MFMA for the X increment); otherwise vector
  *                         ALUs (pass B with its N x N coefficients staged in LDS);
  *                         2: vector kernels with LDS-staged coefficients (both
  *                         passes); 3: vector kernels reading the coefficients

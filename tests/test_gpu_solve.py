@@ -396,8 +396,10 @@ def test_site_orders_match_oracle(order, dims):
 @pytest.mark.parametrize("n", [5, 16, 17, 32, 40, 64])
 def test_pass_kernels_match_oracle(n):
     """Matrix-core (FP64 MFMA, transposed column tiles, triangular K-steps skipped;
-    used for 16 < N <= 32), LDS-staged vector and scalar-load vector passes A and B
-    give the oracle's iterates (FP64, FP32) and converged solves (FP32, FP16, BF16)."""
+    used for 16 < N <= 32, pass A in FP64 also for 32 < N <= 64, and the FP32-MFMA
+    forms for FP32 at 32 < N <= 64), LDS-staged vector and scalar-load vector passes A
+    and B give the oracle's iterates (FP64, FP32) and converged solves (FP32, FP16,
+    BF16)."""
     dims = (6, 6, 6, 8)
     fat, lng, B = inputs(dims, True, n, 7300 + n)
     m = 0.15
