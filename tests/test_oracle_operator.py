@@ -210,3 +210,36 @@ def test_smooth_links_are_su3_and_interpolate():
     means = [np.mean(np.real(np.trace(synth.smooth_su3(synth.make_rng(74), (2000,), e), axis1=1, axis2=2))) / 3
              for e in (0.2, 0.6, 1.2)]
     assert means[0] > means[1] > means[2] and 0.7 < means[1] < 0.9
+
+
+def test_diluted_noise_sources_partition():
+    """The diluted sources (Sec. 7.1): for every noise vector, the n_subsets pieces have
+    disjoint supports that together cover every even site; every nonzero component is
+    a fourth root of unity; piece s holds exactly the even sites whose spatial corner
+    (x mod 2) + 2 (y mod 2) + 4 (z mod 2) is s, found here by walking the coordinates."""
+    dims = (4, 2, 4, 6)
+    Lx, Ly, Lz, Lt = dims
+    n_src, n_sub = 3, 8
+    S = synth.diluted_noise_sources(dims, n_src, n_sub, synth.make_rng(91))
+    vh = synth.volume(dims) // 2
+    assert S.shape == (n_src * n_sub, vh, 3)
+    nz = np.abs(S) > 0
+    roots = np.array([1, 1j, -1, -1j])
+    assert np.all(np.min(np.abs(S[nz][:, None] - roots[None, :]), axis=1) < 1e-15)
+    expect = {s: set() for s in range(n_sub)}
+    for t in range(Lt):
+        for z in range(Lz):
+            for y in range(Ly):
+                for x in range(Lx):
+                    if (x + y + z + t) % 2 == 0:
+                        lex = x + Lx * (y + Ly * (z + Lz * t))
+                        expect[(x % 2) + 2 * (y % 2) + 4 * (z % 2)].add(lex >> 1)
+    for k in range(n_src):
+        pieces = S[k * n_sub:(k + 1) * n_sub]
+        support = nz[k * n_sub:(k + 1) * n_sub].all(axis=2)
+        assert np.all(nz[k * n_sub:(k + 1) * n_sub].any(axis=2) == support)   # whole colour vectors
+        assert np.all(support.sum(axis=0) == 1)                               # disjoint and covering
+        for s in range(n_sub):
+            assert set(np.nonzero(support[s])[0]) == expect[s]
+        total = pieces.sum(axis=0)
+        assert np.all(np.abs(np.abs(total) - 1) < 1e-15)
