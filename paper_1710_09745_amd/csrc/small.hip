@@ -149,14 +149,21 @@ __device__ bool chol_inv_lower(Z2* A, Z2* Zm, int N, const double* diag, Z2* col
     return true;
 }
 
-// chol_inv_lower with two buffers per matrix: step k reads (X, ZX) and writes
-// (Y, ZY), then the roles swap, every thread forming the scaled column-k factors it
-// needs itself, so one barrier per step.  The same products as chol_inv_lower.
-// All LDS operands of a step are read before the pivot's square root (the reads
-// do not depend on it), and the breakdown test follows the step's barrier (a
-// failed step's outputs are discarded).  On return *L and *Zout point at the
-// buffers holding L (lower, strict upper zeroed) and L^{-1}; ok = false on a
-// breakdown pivot (same rule as chol_inv_lower).
+// chol_inv_lower with two buffers per matrix and 2 x 2 pivot blocks: step k reads
+// (X, ZX) and writes (Y, ZY), then the roles swap, so one barrier per step and half
+// the steps.  A step does two columns k, k + 1 of the right-looking factorisation at
+// once (the same products as two single-column steps): with l00 = sqrt(a00),
+// l10 = a10 / l00, d1 = a11 - |l10|^2 and l11 = sqrt(d1),
+//   L[i][k] = a_ik / l00,  L[i][k+1] = (a_i,k+1 - L[i][k] conj(l10)) / l11,
+//   A[i][j] -= L[i][k] conj(L[j][k]) + L[i][k+1] conj(L[j][k+1])   (i >= j > k + 1),
+// and on the rows of Z = L^{-1}: Z[k] /= l00, Z[k+1] = (Z[k+1] - l10 Z[k]) / l11,
+// Z[i] -= L[i][k] Z[k] + L[i][k+1] Z[k+1] (i > k + 1).  Every thread forms the
+// factors of its own row and column itself.  An odd last column is a single step
+// (the same formulas with a10 = 0, a11 = 1).  The breakdown test (either pivot, d_k
+// or d1, not positive, not finite or, when diag != nullptr, not above 1e-14 of the
+// column's original diagonal) follows the step's barrier; a failed step's outputs are
+// discarded.  On return *L and *Zout point at the buffers holding L (lower, strict
+// upper zeroed) and L^{-1}.  Only the lower triangles are written and read.
 __device__ void chol_inv_lower_pp(Z2* X, Z2* Y, Z2* ZX, Z2* ZY, int N, const double* diag, bool& ok,
                                   Z2** L, Z2** Zout) {
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
@@ -164,40 +171,64 @@ __device__ void chol_inv_lower_pp(Z2* X, Z2* Y, Z2* ZX, Z2* ZY, int N, const dou
         ZX[e] = Z2{i == j ? 1.0 : 0.0, 0.0};
     }
     __syncthreads();
-    for (int k = 0; k < N; ++k) {
-        const double d = X[k * N + k].re;
-        const double rs = 1.0 / sqrt(d);
+    for (int k = 0; k < N;) {
+        const bool two = k + 1 < N;
+        const int k1 = two ? k + 1 : k;   // column k + 1 (only read when two)
+        const double a00 = X[k * N + k].re;
+        const Z2 a10 = two ? X[k1 * N + k] : Z2{0.0, 0.0};
+        const double a11 = two ? X[k1 * N + k1].re : 1.0;
+        const double r0 = 1.0 / sqrt(a00);
+        const Z2 l10{a10.re * r0, a10.im * r0};
+        const double d1 = a11 - (l10.re * l10.re + l10.im * l10.im);
+        const double r1 = 1.0 / sqrt(d1);
         for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
             const int i = row_of(e, N), j = e - i * N;
-            const Z2 xe = X[e], a = X[i * N + k], b = X[j * N + k], ze = ZX[e], zk = ZX[k * N + j];
-            // L part (lower triangle only; the strict upper triangle is never read)
-            if (j <= i) {
-                Z2 v = xe;
-                if (j == k) {
-                    v = (i == k) ? Z2{d * rs, 0.0} : Z2{v.re * rs, v.im * rs};
-                } else if (j > k) {
-                    const Z2 p = zmul(Z2{a.re * rs, a.im * rs}, zconj(Z2{b.re * rs, b.im * rs}));
-                    v.re -= p.re;
-                    v.im -= p.im;
-                }
-                Y[e] = v;
+            if (j > i) continue;   // strict upper triangles: never written or read
+            const Z2 xe = X[e], ze = ZX[e];
+            const Z2 zero{0.0, 0.0};
+            const Z2 ai0 = i >= k ? X[i * N + k] : zero, ai1 = two && i >= k1 ? X[i * N + k1] : zero;
+            const Z2 aj0 = j > k1 ? X[j * N + k] : zero, aj1 = j > k1 ? X[j * N + k1] : zero;
+            // row k of Z is zero right of its diagonal (j = k + 1 lies in the unread upper part)
+            const Z2 zk0 = j <= k ? ZX[k * N + j] : zero, zk1 = two ? ZX[k1 * N + j] : zero;
+            // this thread's row and column of the two new L columns (i, j >= k)
+            const Z2 li0{ai0.re * r0, ai0.im * r0}, lj0{aj0.re * r0, aj0.im * r0};
+            const Z2 ti = zmul(li0, zconj(l10)), tj = zmul(lj0, zconj(l10));
+            const Z2 li1{(ai1.re - ti.re) * r1, (ai1.im - ti.im) * r1};
+            const Z2 lj1{(aj1.re - tj.re) * r1, (aj1.im - tj.im) * r1};
+            // L part
+            Z2 v = xe;
+            if (j == k) {
+                v = (i == k) ? Z2{a00 * r0, 0.0} : li0;
+            } else if (two && j == k1) {
+                v = (i == k1) ? Z2{d1 * r1, 0.0} : li1;
+            } else if (j > k1) {
+                const Z2 p = zmul(li0, zconj(lj0)), q = zmul(li1, zconj(lj1));
+                v.re -= p.re + q.re;
+                v.im -= p.im + q.im;
             }
-            // Z part: row k scaled, rows below k updated with the scaled row k
-            if (j <= k || j <= i) {
-                Z2 z = ze;
-                if (i == k && j <= k) {
-                    z = Z2{z.re * rs, z.im * rs};
-                } else if (i > k && j <= k) {
-                    const Z2 p = zmul(Z2{a.re * rs, a.im * rs}, Z2{zk.re * rs, zk.im * rs});
-                    z.re -= p.re;
-                    z.im -= p.im;
+            Y[e] = v;
+            // Z part: rows k, k + 1 of the pivot block, then the rows below it
+            Z2 z = ze;
+            if (j <= k1) {
+                const Z2 zn0{zk0.re * r0, zk0.im * r0};
+                const Z2 t = zmul(l10, zn0);
+                const Z2 zn1{(zk1.re - t.re) * r1, (zk1.im - t.im) * r1};
+                if (i == k) {
+                    z = zn0;
+                } else if (two && i == k1) {
+                    z = zn1;
+                } else if (i > k1) {
+                    const Z2 p = zmul(li0, zn0), q = zmul(li1, zn1);
+                    z.re -= p.re + q.re;
+                    z.im -= p.im + q.im;
                 }
-                ZY[e] = z;
             }
+            ZY[e] = z;
         }
         __syncthreads();
-        const double floor_k = diag ? 1e-14 * diag[k] : 0.0;
-        if (!(d > floor_k) || !isfinite(d)) {
+        const double f0 = diag ? 1e-14 * diag[k] : 0.0;
+        const double f1 = (diag && two) ? 1e-14 * diag[k1] : 0.0;
+        if (!(a00 > f0) || !isfinite(a00) || (two && (!(d1 > f1) || !isfinite(d1)))) {
             ok = false;
             *L = X;
             *Zout = ZX;
@@ -209,6 +240,7 @@ __device__ void chol_inv_lower_pp(Z2* X, Z2* Y, Z2* ZX, Z2* ZY, int N, const dou
         t = ZX;
         ZX = ZY;
         ZY = t;
+        k += two ? 2 : 1;
     }
     for (int e = threadIdx.x; e < N * N; e += blockDim.x)
         if (strict_upper(e, N)) X[e] = Z2{0.0, 0.0};
