@@ -334,6 +334,114 @@ def block_cg_rq(apply_A, B, tol, max_iter=100000, X0=None, ru_delta=0.0, sloppy=
     return from_mat(Y, vh), info
 
 
+def sstep_block_cg(apply_A, B, s, tol, lam, max_outer=100000, basis="chebyshev", trace=None):
+    """s-step block CG: every outer iteration extends the search space by s block
+    Krylov directions at once, so that all of its inner products form one
+    reduction phase per s steps instead of two per step -- the s-step methods that
+    Sec. 8 proposes for block solvers (Chronopoulos and Gear's s-step CG, with N
+    columns per direction).
+
+    Outer iteration k, with R_k the L x N block residual and K = s N columns:
+      basis       V = [V_0 ... V_{s-1}], V_0 = R_k, each V_j = p_j(A) R_k with p_j of
+                  degree j: the Chebyshev polynomials of the interval
+                  lam = (lmin, lmax) (c = (lmax + lmin) / 2, h = (lmax - lmin) / 2;
+                  V_1 = (A V_0 - c V_0) / h, V_{j+1} = 2 (A V_j - c V_j) / h - V_{j-1}),
+                  or the monomials V_{j+1} = A V_j (basis="monomial");  AV = A V
+      reduction   Gv = V^H AV and Gr = V^H R_k; after the first outer iteration also
+                  Ga = (A P_{k-1})^H V, Wp = P_{k-1}^H A P_{k-1} and Pr = P_{k-1}^H R_k
+      directions  first outer iteration (and after a restart): P = V, AP = AV,
+                  W = Gv, g = Gr;  otherwise Bk = -Wp^{-1} Ga (P A-orthogonal to
+                  P_{k-1}), P = V + P_{k-1} Bk, AP = AV + AP_{k-1} Bk,
+                  W = Gv + Ga^H Bk (= P^H A P) and g = Gr + Bk^H Pr (= P^H R_k)
+      step        alpha = W^{-1} g, X = X + P alpha, R = R_k - AP alpha.
+    In exact arithmetic Pr = 0, Wp is the previous W and X after k outer
+    iterations is the Galerkin solution over X0 + K_{ks}(A, R_0), i.e. blockCGrQ's
+    X after k s iterations, whatever the basis polynomials.  In floating point the
+    recurrence needs the freshly reduced Wp and Pr: carrying W over, or dropping Pr,
+    breaks down for s >= 3 on the 4^4 test operators (the instability of s-step
+    methods that Sec. 8 anticipates).
+
+    The stopping test runs on the iterated residual at the top of each outer
+    iteration (max_i ||r_i|| / ||b_i|| <= tol), then on the true residual
+    B - A X; if that misses tol, the recurrence restarts from it (P discarded).
+    max_outer bounds the outer iterations.
+    trace: optional list; per outer iteration a dict with Bk, W and alpha.
+
+    Returns (X [N][V/2][3], SolveInfo(iters = outer iterations * s, outer,
+    restarts, converged, true_rel_res)).
+    Raises Breakdown when Wp or W is not positive definite.
+    """
+    B = np.asarray(B, dtype=np.complex128)
+    n, vh = B.shape[0], B.shape[1]
+    if s < 1:
+        raise ValueError("s must be at least 1")
+
+    def A(M):
+        return to_mat(apply_A(from_mat(M, vh)))
+
+    lmin, lmax = float(lam[0]), float(lam[1])
+    c, h = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    Bm = to_mat(B)
+    bnorm = np.linalg.norm(Bm, axis=0)
+    if np.any(bnorm == 0):
+        raise ValueError("zero right-hand side column")
+    X = np.zeros_like(Bm)
+    R = Bm.copy()
+    P = AP = None
+    outer = restarts = 0
+    converged = False
+    true_rel = np.linalg.norm(R, axis=0) / bnorm
+    while True:
+        if np.max(np.linalg.norm(R, axis=0) / bnorm) <= tol:
+            Rt = Bm - A(X)
+            true_rel = np.linalg.norm(Rt, axis=0) / bnorm
+            if true_rel.max() <= tol:
+                converged = True
+                break
+            R, P, AP = Rt, None, None
+            restarts += 1
+        if outer >= max_outer:
+            break
+        # the s basis blocks and their images under A
+        Vb, AVb = [R], []
+        for j in range(s):
+            AVb.append(A(Vb[j]))
+            if j + 1 < s:
+                if basis == "monomial":
+                    Vb.append(AVb[j])
+                elif j == 0:
+                    Vb.append((AVb[0] - c * Vb[0]) / h)
+                else:
+                    Vb.append(2.0 * (AVb[j] - c * Vb[j]) / h - Vb[j - 1])
+        V, AV = np.hstack(Vb), np.hstack(AVb)
+        Gv = V.conj().T @ AV
+        Gr = V.conj().T @ R
+        if P is None:
+            Bk = np.zeros((s * n, s * n), dtype=np.complex128)
+            P, AP, W, g = V, AV, Gv, Gr
+        else:
+            Ga = AP.conj().T @ V
+            Wp = P.conj().T @ AP
+            Pr = P.conj().T @ R
+            Bk = -hpd_inverse(0.5 * (Wp + Wp.conj().T)) @ Ga
+            P = V + P @ Bk
+            AP = AV + AP @ Bk
+            W = Gv + Ga.conj().T @ Bk
+            g = Gr + Bk.conj().T @ Pr
+        W = 0.5 * (W + W.conj().T)
+        alpha = hpd_inverse(W) @ g
+        X = X + P @ alpha
+        R = R - AP @ alpha
+        outer += 1
+        if trace is not None:
+            trace.append(dict(Bk=Bk, W=W, alpha=alpha))
+    if not converged:
+        true_rel = np.linalg.norm(Bm - A(X), axis=0) / bnorm
+    info = SolveInfo(iters=outer * s, outer=outer, restarts=restarts, converged=converged,
+                     true_rel_res=true_rel)
+    return from_mat(X, vh), info
+
+
 def cg(apply_A, b, tol, max_iter=100000):
     """Textbook Hestenes-Stiefel CG for one right-hand side b [V/2][3] (the baseline, Sec. 7.1).
 
