@@ -188,6 +188,36 @@ int bcg_solve_cg(bcg_ctx *ctx, const void *B, void *X, int nrhs, bcg_stats *stat
  * Same arguments and returns as bcg_solve_cg. */
 int bcg_solve_pseudo(bcg_ctx *ctx, const void *B, void *X, int nrhs, bcg_stats *stats);
 
+/* s-step block CG, the extension Sec. 8 proposes so that a block solver needs
+ * fewer than one reduction per iteration (Chronopoulos and Gear's s-step CG with
+ * nrhs columns per direction).  Each outer iteration builds the basis
+ * V = [R, p_1(A) R, ..., p_{s-1}(A) R] of s nrhs columns (p_j the Chebyshev
+ * polynomials of the interval [lmin, lmax], two-term recurrence from A V_j),
+ * reduces all of its inner products in one phase (V^H A V, V^H V and, against
+ * the previous direction block P', (A P')^H V, P'^H A P', P'^H V), forms the
+ * coefficients in one workgroup, then updates P = V + P' Bk (A-orthogonal to
+ * P'), A P, X += P alpha and R -= A P alpha.  In exact arithmetic k outer
+ * iterations give the iterate of k s block-CG iterations; in floating point the
+ * basis loses conditioning as s grows and the iteration count rises.  The
+ * iterated residual is tested at the top of each outer iteration; when it meets
+ * tol the FP64 true residual is checked and, if a column misses, the recurrence
+ * restarts from the true residual.  FP64 storage and arithmetic regardless of
+ * bcg_set_solver's sloppy_prec; tol and max_iter (counted in s-steps, rounded
+ * down to whole outer iterations) come from bcg_set_solver.
+ *   s:    directions per outer iteration; s * nrhs <= 64 (BCG_ERR_ARG otherwise)
+ *   lmin: lower end of the basis interval; <= 0 selects 4 m^2, the smallest
+ *         possible eigenvalue of A
+ *   lmax: upper end; <= 0 selects 1.1 times a 30-step power-iteration estimate
+ *         of the largest eigenvalue from the first column (lmin < lmax required
+ *         when both are given)
+ * stats->iters counts s-steps (outer iterations times s), stats->restarts the
+ * true-residual restarts.  Returns BCG_OK, BCG_ERR_NOT_CONVERGED or
+ * BCG_ERR_BREAKDOWN (a direction Gram P^H A P not positive definite: the basis
+ * lost rank; X holds the last iterate), or an argument / runtime error.  Same
+ * vector arguments as bcg_solve with X0 = 0. */
+int bcg_solve_sstep(bcg_ctx *ctx, const void *B, void *X, int nrhs, int s, double lmin, double lmax,
+                    bcg_stats *stats);
+
 /* Link force: the gradients w.r.t. the fat and long links of a loss L with
  * dL = -Re sum_i Lam_i^H dA X_i (X = A^{-1} B, Lam = A^{-1} dL/dX), in the
  * complex convention grad = dL/dRe + i dL/dIm and without projection:

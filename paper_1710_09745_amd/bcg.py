@@ -83,6 +83,7 @@ def load_library():
         "bcg_solve": ([P, P, P, I, I, ctypes.POINTER(Stats)], I),
         "bcg_solve_cg": ([P, P, P, I, ctypes.POINTER(Stats)], I),
         "bcg_solve_pseudo": ([P, P, P, I, ctypes.POINTER(Stats)], I),
+        "bcg_solve_sstep": ([P, P, P, I, I, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Stats)], I),
         "bcg_link_force": ([P, P, P, I, P, P], I),
         "bcg_set_profiling": ([P, U], I),
         "bcg_set_option": ([P, I, I], I),
@@ -276,6 +277,18 @@ class Context:
         _vec(B, "B", vh=self.Vh)
         X = torch.empty_like(B)
         rc, info = self._solve(self.lib.bcg_solve_pseudo, B, X)
+        if raise_on_error:
+            self._check(rc)
+        info["rc"] = rc
+        return X, info
+
+    def solve_sstep(self, B, s, lmin=0.0, lmax=0.0, raise_on_error=True):
+        """s-step block CG with s block directions per outer iteration (s * N <= 64)
+        and a Chebyshev basis on [lmin, lmax] (<= 0: 4 m^2, and 1.1 times a
+        power-iteration estimate).  Returns (X, info); info["iters"] counts s-steps."""
+        _vec(B, "B", vh=self.Vh)
+        X = torch.empty_like(B)
+        rc, info = self._solve(self.lib.bcg_solve_sstep, B, X, int(s), float(lmin), float(lmax))
         if raise_on_error:
             self._check(rc)
         info["rc"] = rc

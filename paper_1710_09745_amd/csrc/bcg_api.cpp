@@ -11,6 +11,7 @@
 // final true-residual check.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -286,10 +287,20 @@ int gram_partials(bcg_ctx* ctx, Prec p, const void* A, const void* B, int N, dou
     return BCG_OK;
 }
 
-// out = A^H B  (N x N, FP64, leading dimension 64)
+// out = A^H B  (N x N, FP64, leading dimension 64) for a Hermitian A^H B (the
+// matrix-core kernel forms the upper tiles only)
 int gram(bcg_ctx* ctx, Prec p, const void* A, const void* B, int N, double2* out, const int* halt) {
     RETCK(gram_partials(ctx, p, A, B, N, ctx->partials, halt));
     return reduce(ctx, ctx->partials, gram_parts(N, (int)ctx->Vh, gram_mfma(ctx)), nullptr, 0, 0.0, N, out, halt);
+}
+
+// out = A^H B for any A, B (the vector-ALU Gram, which forms every tile)
+int gram_general(bcg_ctx* ctx, const double2* A, const double2* B, int N, double2* out) {
+    {
+        Prof pr(ctx, BCG_K_GRAM);
+        HIPCK(launch_gram(Prec::FP64, A, B, N, (int)ctx->Vh, ctx->partials, nullptr, false, ctx->stream));
+    }
+    return reduce(ctx, ctx->partials, gram_parts(N, (int)ctx->Vh, false), nullptr, 0, 0.0, N, out, nullptr);
 }
 
 int colnorms(bcg_ctx* ctx, const double2* V, int N, double* out) {
@@ -1359,6 +1370,171 @@ int bcg_solve_pseudo(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, bcg_stat
         for (int i = 0; i < N; ++i) tr[i] = ctx->h_vec[i] / bn[i];
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_stats(stats, ctx->h_pb->iters, 0, status, restarts, secs, tr, N);
+    return status;
+}
+
+// ---------------------------------------------------------------------------------------------
+// s-step block CG: s block Krylov directions per outer iteration, one reduction phase
+// ---------------------------------------------------------------------------------------------
+int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_steps, double lmin, double lmax,
+                    bcg_stats* stats) {
+    if (!ctx) return BCG_ERR_ARG;
+    if (!B || !Xout) return fail(ctx, BCG_ERR_ARG, "null vector pointer");
+    RETCK(check_nrhs(ctx, nrhs));
+    RETCK(check_ready(ctx));
+    if (s_steps < 1 || (long)s_steps * nrhs > BCG_MAX_RHS)
+        return fail(ctx, BCG_ERR_ARG, "s * nrhs must be in [1, 64], got s = " + std::to_string(s_steps));
+    if (!std::isfinite(lmin) || !std::isfinite(lmax) || (lmax > 0.0 && lmin >= lmax))
+        return fail(ctx, BCG_ERR_ARG, "the basis interval needs finite lmin < lmax");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int N = nrhs, S = s_steps, K = S * N;
+    const int Vh = (int)ctx->Vh;
+    const long n = nvec(ctx, N), n1 = 3L * Vh;
+    hipStream_t s = ctx->stream;
+    RETCK(alloc_solve(ctx, N, Prec::FP64));
+    const size_t bK = (size_t)nvec(ctx, K) * 16;
+    for (int slot : {WB_P0, WB_P1, WB_Q0, WB_Q1, WB_AP, WB_T}) RETCK(ensure(ctx, slot, bK));
+    double2 *B64 = Wd(ctx, WB_B64), *X = Wd(ctx, WB_Y), *R = Wd(ctx, WB_R64), *T64 = Wd(ctx, WB_T64),
+            *Rt = Wd(ctx, WB_X);
+    double2 *V = Wd(ctx, WB_P0), *AV = Wd(ctx, WB_P1);
+    double2 *Pp = Wd(ctx, WB_Q0), *Pn = Wd(ctx, WB_Q1), *APp = Wd(ctx, WB_AP), *APn = Wd(ctx, WB_T);
+    double2 *Gv = M(ctx, M_G), *Gvv = M(ctx, M_H), *Ga = M(ctx, M_BETA), *Wpm = M(ctx, M_BETAC),
+            *Pv = M(ctx, M_C), *Bk = M(ctx, M_CINV), *alpha = M(ctx, M_SINV), *nalpha = M(ctx, M_SH);
+    int* d_status = ctx->d_flags + 1;
+    double* d_rn = ctx->d_vec + 2 * MAXN;   // iterated residual norms
+    double* d_lam = ctx->d_vec + 3 * MAXN;  // power-iteration estimate
+    double* d_true = ctx->d_vec + MAXN;
+    {
+        Prof pr(ctx, BCG_K_CONVERT);
+        HIPCK(launch_canon_to_int((const double2*)B, B64, N, Vh, s));
+    }
+    RETCK(colnorms(ctx, B64, N, ctx->d_vec));
+    HIPCK(hipMemcpyAsync(ctx->h_vec, ctx->d_vec, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    RETCK(sync(ctx));
+    double bn[MAXN];
+    for (int i = 0; i < N; ++i) {
+        bn[i] = ctx->h_vec[i];
+        if (!(bn[i] > 0.0) || !std::isfinite(bn[i]))
+            return fail(ctx, BCG_ERR_ARG, "right-hand side column " + std::to_string(i) + " is zero or not finite");
+    }
+    // the basis interval: lmin defaults to 4 m^2 (the bound of A = 4 m^2 + D_oe^H D_oe),
+    // lmax to 1.1 times a 30-step power-iteration estimate from the first column
+    if (!(lmin > 0.0)) lmin = 4.0 * ctx->mass * ctx->mass;
+    if (!(lmax > 0.0)) {
+        for (int slot : {WB_A0, WB_A1}) RETCK(ensure(ctx, slot, (size_t)n1 * 16));
+        double2 *pv = Wd(ctx, WB_A0), *pw = Wd(ctx, WB_A1);
+        HIPCK(launch_scale_inv(pv, B64, ctx->d_vec, n1, s));
+        for (int it = 0; it < 30; ++it) {
+            RETCK(apply64(ctx, pv, pw, T64, 1, nullptr));
+            RETCK(colnorms(ctx, pw, 1, d_lam));
+            HIPCK(launch_scale_inv(pv, pw, d_lam, n1, s));
+        }
+        HIPCK(hipMemcpyAsync(ctx->h_vec, d_lam, sizeof(double), hipMemcpyDeviceToHost, s));
+        RETCK(sync(ctx));
+        lmax = 1.1 * ctx->h_vec[0];
+        if (!(lmax > lmin) || !std::isfinite(lmax)) lmax = 2.0 * lmin + 1.0;
+    }
+    const double cc = 0.5 * (lmax + lmin), hh = 0.5 * (lmax - lmin);
+    HIPCK(launch_zero(X, n * 16, s));
+    HIPCK(launch_copy(B64, R, n * 16, s));
+    HIPCK(hipMemsetAsync(d_status, 0, sizeof(int), s));
+    const int max_outer = std::max(1, ctx->max_iter / S);
+    int status = BCG_OK, outer = 0, restarts = 0;
+    bool first = true;
+    double tr[MAXN];
+    for (;;) {
+        RETCK(colnorms(ctx, R, N, d_rn));
+        HIPCK(hipMemcpyAsync(ctx->h_vec, d_rn, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(ctx->h_flags, d_status, sizeof(int), hipMemcpyDeviceToHost, s));
+        RETCK(sync(ctx));
+        if (ctx->h_flags[0] != 0) {
+            status = BCG_ERR_BREAKDOWN;
+            fail(ctx, status, ctx->h_flags[0] == 1 ? "s-step breakdown: P'^H A P' not positive definite"
+                                                   : "s-step breakdown: P^H A P not positive definite");
+            break;
+        }
+        double mx = 0.0;
+        for (int i = 0; i < N; ++i) mx = std::fmax(mx, ctx->h_vec[i] / bn[i]);
+        if (ctx->monitor) ctx->monitor(ctx->monitor_user, outer * S, restarts, mx);
+        if (mx <= ctx->tol) {
+            // converged on the iterated residual: check the true residual
+            RETCK(apply64(ctx, X, Rt, T64, N, nullptr));
+            HIPCK(launch_residual(B64, Rt, n, s));
+            RETCK(colnorms(ctx, Rt, N, d_true));
+            HIPCK(hipMemcpyAsync(ctx->h_vec, d_true, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+            RETCK(sync(ctx));
+            double tm = 0.0;
+            for (int i = 0; i < N; ++i) {
+                tr[i] = ctx->h_vec[i] / bn[i];
+                tm = std::fmax(tm, tr[i]);
+            }
+            if (tm <= ctx->tol) break;
+            // restart the recurrence from the true residual
+            HIPCK(launch_copy(Rt, R, n * 16, s));
+            first = true;
+            restarts += 1;
+        }
+        if (outer >= max_outer) {
+            status = BCG_ERR_NOT_CONVERGED;
+            fail(ctx, status, "max_iter reached in s-step block CG");
+            break;
+        }
+        // basis V = [R, p_1(A) R, ...] (Chebyshev polynomials of [lmin, lmax]) and AV = A V
+        HIPCK(launch_copy(R, V, n * 16, s));
+        for (int j = 0; j < S; ++j) {
+            RETCK(apply64(ctx, V + j * n, AV + j * n, T64, N, nullptr));
+            if (j + 1 < S) {
+                Prof pr(ctx, BCG_K_OTHER);
+                HIPCK(launch_cheb_step(V + (j + 1) * n, AV + j * n, V + j * n, j ? V + (j - 1) * n : nullptr,
+                                       (j ? 2.0 : 1.0) / hh, cc, n, s));
+            }
+        }
+        // one reduction phase: the Hermitian V^H AV, V^H V, P'^H AP' on the matrix
+        // cores, the general (AP')^H V and P'^H V on the vector ALUs
+        RETCK(gram(ctx, Prec::FP64, V, AV, K, Gv, nullptr));
+        RETCK(gram(ctx, Prec::FP64, V, V, K, Gvv, nullptr));
+        if (!first) {
+            RETCK(gram_general(ctx, APp, V, K, Ga));
+            RETCK(gram(ctx, Prec::FP64, Pp, APp, K, Wpm, nullptr));
+            RETCK(gram_general(ctx, Pp, V, K, Pv));
+        }
+        {
+            Prof pr(ctx, BCG_K_SMALL);
+            HIPCK(launch_sstep_coef(Gv, Gvv, Ga, Wpm, Pv, Bk, alpha, nalpha, d_status, K, N, first ? 1 : 0, s));
+        }
+        {
+            // P = V + P' Bk, AP = AV + AP' Bk, X += P alpha, R -= AP alpha
+            Prof pr(ctx, BCG_K_PASS_B);
+            if (first) {
+                HIPCK(launch_copy(V, Pn, (long)bK, s));
+                HIPCK(launch_copy(AV, APn, (long)bK, s));
+            } else {
+                HIPCK(launch_bmul(Prec::FP64, Pp, Prec::FP64, V, Pn, Bk, K, Vh, d_status, s));
+                HIPCK(launch_bmul(Prec::FP64, APp, Prec::FP64, AV, APn, Bk, K, Vh, d_status, s));
+            }
+            HIPCK(launch_bmul_rect(Pn, X, X, alpha, K, N, Vh, d_status, s));
+            HIPCK(launch_bmul_rect(APn, R, R, nalpha, K, N, Vh, d_status, s));
+        }
+        std::swap(Pp, Pn);
+        std::swap(APp, APn);
+        first = false;
+        outer += 1;
+    }
+    if (status != BCG_OK) {
+        RETCK(apply64(ctx, X, Rt, T64, N, nullptr));
+        HIPCK(launch_residual(B64, Rt, n, s));
+        RETCK(colnorms(ctx, Rt, N, d_true));
+        HIPCK(hipMemcpyAsync(ctx->h_vec, d_true, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    }
+    {
+        Prof pr(ctx, BCG_K_CONVERT);
+        HIPCK(launch_int_to_canon(X, (double2*)Xout, N, Vh, s));
+    }
+    RETCK(sync(ctx));
+    if (status != BCG_OK)
+        for (int i = 0; i < N; ++i) tr[i] = ctx->h_vec[i] / bn[i];
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(stats, outer * S, 0, status, restarts, secs, tr, N);
     return status;
 }
 

@@ -1518,13 +1518,13 @@ __global__ void __launch_bounds__(256)
 k_bmul(const typename SX::pair* __restrict__ X, const float* __restrict__ Xs,
        const typename SY::pair* __restrict__ Z, const float* __restrict__ Zs,
        typename SY::pair* __restrict__ Y, float* __restrict__ Ys, const double2* __restrict__ M, int N,
-       int Vh, const int* __restrict__ skip) {
+       int Nout, int Vh, const int* __restrict__ skip) {
     if (skip != nullptr && *skip) return;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar coefficient loads
     const int i = blockIdx.x * 64 + lane;
     if (i >= Vh) return;
-    for (int j0 = wave * CPT; j0 < N; j0 += 4 * CPT) {
+    for (int j0 = wave * CPT; j0 < Nout; j0 += 4 * CPT) {
         C2<double> acc[CPT][3];
 #pragma unroll
         for (int m = 0; m < CPT; ++m)
@@ -1536,7 +1536,7 @@ k_bmul(const typename SX::pair* __restrict__ X, const float* __restrict__ Xs,
             load_group<SX, 3>(X, Xs, Vh, l, i, a);
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
-                if (j0 + m < N) {
+                if (j0 + m < Nout) {
                     const C2<double> b = dld(M + l * MAXN + j0 + m);
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
@@ -1546,7 +1546,7 @@ k_bmul(const typename SX::pair* __restrict__ X, const float* __restrict__ Xs,
         }
 #pragma unroll
         for (int m = 0; m < CPT; ++m) {
-            if (j0 + m < N) {
+            if (j0 + m < Nout) {
                 if (Z != nullptr) {
                     C2<typename SY::real> z[3];
                     load_group<SY, 3>(Z, Zs, Vh, j0 + m, i, z);
@@ -1563,24 +1563,30 @@ k_bmul(const typename SX::pair* __restrict__ X, const float* __restrict__ Xs,
 }
 
 template <typename SX, typename SY>
-static void bmul_t(const void* X, const void* Z, void* Y, const double2* M, int N, int Vh, const int* skip,
-                   hipStream_t s) {
+static void bmul_t(const void* X, const void* Z, void* Y, const double2* M, int N, int Nout, int Vh,
+                   const int* skip, hipStream_t s) {
     dim3 grid((Vh + 63) / 64);
     hipLaunchKernelGGL((k_bmul<SX, SY, 4>), grid, dim3(256), 0, s, (const typename SX::pair*)X,
-                       scale_of<SX>(X, N, 3, Vh), (const typename SY::pair*)Z, scale_of<SY>(Z, N, 3, Vh),
-                       (typename SY::pair*)Y, scale_of<SY>(Y, N, 3, Vh), M, N, Vh, skip);
+                       scale_of<SX>(X, N, 3, Vh), (const typename SY::pair*)Z, scale_of<SY>(Z, Nout, 3, Vh),
+                       (typename SY::pair*)Y, scale_of<SY>(Y, Nout, 3, Vh), M, N, Nout, Vh, skip);
 }
 
 template <typename SX>
 static hipError_t bmul_y(Prec py, const void* X, const void* Z, void* Y, const double2* M, int N, int Vh,
                          const int* skip, hipStream_t s) {
     switch (py) {
-        case Prec::FP64: bmul_t<SX, F64>(X, Z, Y, M, N, Vh, skip, s); break;
-        case Prec::FP32: bmul_t<SX, F32>(X, Z, Y, M, N, Vh, skip, s); break;
-        case Prec::FP16: bmul_t<SX, H16>(X, Z, Y, M, N, Vh, skip, s); break;
-        case Prec::BF16: bmul_t<SX, B16>(X, Z, Y, M, N, Vh, skip, s); break;
-        case Prec::FX16: bmul_t<SX, X16>(X, Z, Y, M, N, Vh, skip, s); break;
+        case Prec::FP64: bmul_t<SX, F64>(X, Z, Y, M, N, N, Vh, skip, s); break;
+        case Prec::FP32: bmul_t<SX, F32>(X, Z, Y, M, N, N, Vh, skip, s); break;
+        case Prec::FP16: bmul_t<SX, H16>(X, Z, Y, M, N, N, Vh, skip, s); break;
+        case Prec::BF16: bmul_t<SX, B16>(X, Z, Y, M, N, N, Vh, skip, s); break;
+        case Prec::FX16: bmul_t<SX, X16>(X, Z, Y, M, N, N, Vh, skip, s); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_bmul_rect(const double2* X, const double2* Z, double2* Y, const double2* M, int Nin, int Nout,
+                            int Vh, const int* skip, hipStream_t s) {
+    bmul_t<F64, F64>(X, Z, Y, M, Nin, Nout, Vh, skip, s);
     return hipGetLastError();
 }
 
@@ -1678,6 +1684,42 @@ __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ a, uint4
 hipError_t launch_copy(const void* src, void* dst, long bytes, hipStream_t s) {
     if (bytes % 16) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_copy, dim3(stream_grid(bytes / 16)), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, bytes / 16);
+    return hipGetLastError();
+}
+
+// One step of the Chebyshev basis of the s-step solver:
+// Vn = a (AV - c V) - Vm  (Vm may be NULL = 0), FP64 pairs, n entries
+__global__ void __launch_bounds__(256) k_cheb_step(double2* __restrict__ Vn, const double2* __restrict__ AV,
+                                                   const double2* __restrict__ V, const double2* __restrict__ Vm,
+                                                   double a, double c, long n) {
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+        const double2 av = AV[t], v = V[t];
+        double2 r = make_double2(a * (av.x - c * v.x), a * (av.y - c * v.y));
+        if (Vm != nullptr) {
+            const double2 m = Vm[t];
+            r.x -= m.x;
+            r.y -= m.y;
+        }
+        Vn[t] = r;
+    }
+}
+hipError_t launch_cheb_step(double2* Vn, const double2* AV, const double2* V, const double2* Vm, double a, double c,
+                            long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cheb_step, dim3(stream_grid(n)), dim3(256), 0, s, Vn, AV, V, Vm, a, c, n);
+    return hipGetLastError();
+}
+
+// v = w / *nrm (FP64 pairs, n entries; *nrm > 0 read on the device)
+__global__ void __launch_bounds__(256) k_scale_inv(double2* __restrict__ v, const double2* __restrict__ w,
+                                                   const double* __restrict__ nrm, long n) {
+    const double r = 1.0 / *nrm;
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+        const double2 x = w[t];
+        v[t] = make_double2(x.x * r, x.y * r);
+    }
+}
+hipError_t launch_scale_inv(double2* v, const double2* w, const double* nrm, long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_inv, dim3(stream_grid(n)), dim3(256), 0, s, v, w, nrm, n);
     return hipGetLastError();
 }
 

@@ -79,7 +79,9 @@ enum { EPI_PLAIN_ = 0, EPI_MASS_ = 1, EPI_MASS_DOT_ = 2 };
 
 // blas.hip --------------------------------------------------------------------------------------
 // partials[b][i*NB + j] = sum over the rows of workgroup b of conj(A[row,i]) B[row,j]
-// mfma: matrix-core kernel for N > 8 (vector-ALU kernel otherwise)
+// mfma: matrix-core kernel for N > 8 (vector-ALU kernel otherwise); it forms the
+// 16 x 16 tiles a <= b only and writes the others as their conjugate transpose, so
+// it needs a Hermitian A^H B (the vector kernel forms every entry)
 hipError_t launch_gram(Prec prec, const void* A, const void* B, int N, int Vh, double2* partials,
                        const int* halt, bool mfma, hipStream_t s);
 // out[i*64 + j] = sum_b partials[b][i*NB + j]  (fixed order)
@@ -104,6 +106,14 @@ hipError_t launch_pass_b(Prec prec, double2* X, const void* Qt, const void* P, v
 // Y <- Z + X M  (Z may be NULL = 0; X, Z may alias Y); X in precision px, Y/Z in py
 hipError_t launch_bmul(Prec px, const void* X, Prec py, const void* Z, void* Y, const double2* M,
                        int N, int Vh, const int* skip, hipStream_t s);
+// Y <- Z + X M with X of Nin columns, Y and Z of Nout, M Nin x Nout (leading dimension 64), FP64
+hipError_t launch_bmul_rect(const double2* X, const double2* Z, double2* Y, const double2* M, int Nin, int Nout,
+                            int Vh, const int* skip, hipStream_t s);
+// Vn = a (AV - c V) - Vm (Vm may be NULL), FP64, n pairs: one Chebyshev basis step
+hipError_t launch_cheb_step(double2* Vn, const double2* AV, const double2* V, const double2* Vm, double a, double c,
+                            long n, hipStream_t s);
+// v = w / *nrm, FP64, n pairs (*nrm read on the device)
+hipError_t launch_scale_inv(double2* v, const double2* w, const double* nrm, long n, hipStream_t s);
 // canonical [N][Vh][3] complex128 <-> internal FP64 [N][3][Vh] pairs
 hipError_t launch_canon_to_int(const double2* src, double2* dst, int N, int Vh, hipStream_t s);
 hipError_t launch_int_to_canon(const double2* src, double2* dst, int N, int Vh, hipStream_t s);
@@ -189,6 +199,12 @@ hipError_t small_setup();
 // initial thin QR of R from H = R^H R:  C (upper) and Cinv; relres, rho_ru; halts on breakdown
 hipError_t launch_small_init(const double2* H, double2* C, double2* Cinv, SolveState* st, int N,
                              int req, hipStream_t s);
+// s-step block CG coefficients (one workgroup): Bk, alpha = W^{-1} g, nalpha = -alpha from
+// the Grams Gv = V^H AV, Gvv = V^H V and (first == 0) Ga = (AP')^H V, Wp = P'^H AP',
+// Pv = P'^H V; *status = 1 / 2 on a non-positive pivot of Wp / W.  K = s N <= 64.
+hipError_t launch_sstep_coef(const double2* Gv, const double2* Gvv, const double2* Ga, const double2* Wp,
+                             const double2* Pv, double2* Bk, double2* alpha, double2* nalpha, int* status, int K,
+                             int N, int first, hipStream_t s);
 // beta = G^{-1}, betaC = beta C
 hipError_t launch_small1(const double2* G, const double2* C, double2* beta, double2* betaC,
                          SolveState* st, int N, int req, hipStream_t s);

@@ -751,6 +751,134 @@ k_small_qr2(const double2* __restrict__ H2, double2* __restrict__ Cacc, double2*
 }
 
 // ---------------------------------------------------------------------------------------------
+// ---------------------------------------------------------------------------------------------
+// s-step block CG: the coefficients of one outer iteration (K = s N basis columns)
+//   inputs (global [64][64]): Gv = V^H AV, Gvv = V^H V (its first N columns are
+//   Gr = V^H R, as V_0 = R), and after the first outer iteration Ga = (A P')^H V,
+//   Wp = P'^H A P' and Pv = P'^H V (first N columns: Pr = P'^H R)
+//   first:  Bk = 0, W = Gv, g = Gr
+//   else:   Bk = -Wp^{-1} Ga, W = Gv + Ga^H Bk, g = Gr + Bk^H Pr
+//   out:    Bk (K x K), alpha = W^{-1} g and nalpha = -alpha (K x N)
+// The inverses go through the Cholesky factor L and Z = L^{-1} (W^{-1} = Z^H Z).
+// A non-positive pivot of Wp (status 1) or W (status 2) stops the kernel with
+// *status set; the update kernels that follow take *status as their skip flag.
+// LDS holds two K x K matrices; every K^3 product reads LDS only, and its result
+// goes to a global [64][64] array (nalpha or alpha before they receive their final
+// values) and back into LDS after a barrier, which makes the workgroup's global
+// writes visible to all of its threads.
+// ---------------------------------------------------------------------------------------------
+__device__ void load_full(Z2* A, const double2* M, int K) {
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) A[e] = gld(M + gofs(e, K));
+}
+
+__global__ void __launch_bounds__(1024)
+k_sstep_coef(const double2* __restrict__ Gv, const double2* __restrict__ Gvv, const double2* __restrict__ Ga,
+             const double2* __restrict__ Wp, const double2* __restrict__ Pv, double2* __restrict__ Bk,
+             double2* __restrict__ alpha, double2* __restrict__ nalpha, int* __restrict__ status, int K, int N,
+             int first) {
+    extern __shared__ Z2 sm[];
+    Z2* A = sm;
+    Z2* Zm = sm + K * K;
+    __shared__ Z2 colk[MAXN];
+    if (!first) {
+        load_herm(A, Wp, K);
+        __syncthreads();
+        if (!chol_inv_lower(A, Zm, K, nullptr, colk)) {
+            if (threadIdx.x == 0) *status = 1;
+            return;
+        }
+        load_full(A, Ga, K);
+        __syncthreads();
+        // Y = Z Ga (Z lower triangular) -> nalpha
+        for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+            const int i = row_of(e, K), j = e - i * K;
+            Z2 acc{0.0, 0.0};
+            for (int l = 0; l <= i; ++l) {
+                const Z2 p = zmul(Zm[i * K + l], A[l * K + j]);
+                acc.re += p.re;
+                acc.im += p.im;
+            }
+            gst(nalpha + i * MAXN + j, acc);
+        }
+        __syncthreads();
+        load_full(A, nalpha, K);
+        __syncthreads();
+        // Bk = -Z^H Y
+        for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+            const int i = row_of(e, K), j = e - i * K;
+            Z2 acc{0.0, 0.0};
+            for (int l = i; l < K; ++l) {
+                const Z2 p = zmul(zconj(Zm[l * K + i]), A[l * K + j]);
+                acc.re += p.re;
+                acc.im += p.im;
+            }
+            gst(Bk + i * MAXN + j, Z2{-acc.re, -acc.im});
+        }
+        __syncthreads();
+        load_full(A, Ga, K);
+        load_full(Zm, Bk, K);
+        __syncthreads();
+        // W = Gv + Ga^H Bk -> nalpha;  g = Gr + Bk^H Pr -> alpha
+        for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+            const int i = row_of(e, K), j = e - i * K;
+            Z2 acc = gld(Gv + i * MAXN + j);
+            for (int l = 0; l < K; ++l) {
+                const Z2 p = zmul(zconj(A[l * K + i]), Zm[l * K + j]);
+                acc.re += p.re;
+                acc.im += p.im;
+            }
+            gst(nalpha + i * MAXN + j, acc);
+        }
+        for (int e = threadIdx.x; e < K * N; e += blockDim.x) {
+            const int i = row_of(e, N), n = e - i * N;
+            Z2 acc = gld(Gvv + i * MAXN + n);
+            for (int l = 0; l < K; ++l) {
+                const Z2 p = zmul(zconj(Zm[l * K + i]), gld(Pv + l * MAXN + n));
+                acc.re += p.re;
+                acc.im += p.im;
+            }
+            gst(alpha + i * MAXN + n, acc);
+        }
+        __syncthreads();
+        load_herm(A, nalpha, K);
+    } else {
+        load_herm(A, Gv, K);
+        for (int e = threadIdx.x; e < K * K; e += blockDim.x) gst(Bk + gofs(e, K), Z2{0.0, 0.0});
+        for (int e = threadIdx.x; e < K * N; e += blockDim.x) {
+            const int i = row_of(e, N), n = e - i * N;
+            gst(alpha + i * MAXN + n, gld(Gvv + i * MAXN + n));
+        }
+    }
+    __syncthreads();
+    if (!chol_inv_lower(A, Zm, K, nullptr, colk)) {
+        if (threadIdx.x == 0) *status = 2;
+        return;
+    }
+    // T = Z g (into A, K x N with leading dimension N), then alpha = Z^H T
+    for (int e = threadIdx.x; e < K * N; e += blockDim.x) {
+        const int i = row_of(e, N), n = e - i * N;
+        Z2 acc{0.0, 0.0};
+        for (int l = 0; l <= i; ++l) {
+            const Z2 p = zmul(Zm[i * K + l], gld(alpha + l * MAXN + n));
+            acc.re += p.re;
+            acc.im += p.im;
+        }
+        A[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < K * N; e += blockDim.x) {
+        const int i = row_of(e, N), n = e - i * N;
+        Z2 acc{0.0, 0.0};
+        for (int l = i; l < K; ++l) {
+            const Z2 p = zmul(zconj(Zm[l * K + i]), A[l * N + n]);
+            acc.re += p.re;
+            acc.im += p.im;
+        }
+        gst(alpha + i * MAXN + n, acc);
+        gst(nalpha + i * MAXN + n, Z2{-acc.re, -acc.im});
+    }
+}
+
 static size_t small_lds(int N) { return (small_has_cold(N) ? 5 : 2) * (size_t)N * N * sizeof(Z2); }
 
 hipError_t small_setup() {
@@ -761,6 +889,9 @@ hipError_t small_setup() {
     if ((e = hipFuncSetAttribute((const void*)k_small2, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
     if ((e = hipFuncSetAttribute((const void*)k_small_ru, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
     if ((e = hipFuncSetAttribute((const void*)k_small_qr2, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_sstep_coef, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)(2 * MAXN * MAXN * sizeof(Z2)))) != hipSuccess)
+        return e;
     return hipSuccess;
 }
 
@@ -783,6 +914,14 @@ hipError_t launch_identity(double2* M, int N, hipStream_t s) {
 hipError_t launch_small_init(const double2* H, double2* C, double2* Cinv, SolveState* st, int N,
                              int req, hipStream_t s) {
     hipLaunchKernelGGL(k_small_init, dim3(1), dim3(small_threads(N, req)), small_lds(N), s, H, C, Cinv, st, N);
+    return hipGetLastError();
+}
+hipError_t launch_sstep_coef(const double2* Gv, const double2* Gvv, const double2* Ga, const double2* Wp,
+                             const double2* Pv, double2* Bk, double2* alpha, double2* nalpha, int* status, int K,
+                             int N, int first, hipStream_t s) {
+    if (K < 1 || K > MAXN || N < 1 || N > K) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sstep_coef, dim3(1), dim3(small_threads(K, 0)), 2 * (size_t)K * K * sizeof(Z2), s, Gv, Gvv,
+                       Ga, Wp, Pv, Bk, alpha, nalpha, status, K, N, first);
     return hipGetLastError();
 }
 hipError_t launch_small1(const double2* G, const double2* C, double2* beta, double2* betaC,
