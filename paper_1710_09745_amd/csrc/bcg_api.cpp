@@ -1392,14 +1392,21 @@ int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_ste
     const long n = nvec(ctx, N), n1 = 3L * Vh;
     hipStream_t s = ctx->stream;
     RETCK(alloc_solve(ctx, N, Prec::FP64));
-    const size_t bK = (size_t)nvec(ctx, K) * 16;
-    for (int slot : {WB_P0, WB_P1, WB_Q0, WB_Q1, WB_AP, WB_T}) RETCK(ensure(ctx, slot, bK));
+    // three slots of K columns for the basis V, the previous directions P' and the
+    // new ones (and the same for AV, AP', AP): V always sits next to P', so that
+    // U = [V | P'] (or [P' | V]) is one block of 2K columns
+    const long nK = nvec(ctx, K);
+    for (int slot : {WB_P0, WB_P1}) RETCK(ensure(ctx, slot, (size_t)3 * nK * 16));
     double2 *B64 = Wd(ctx, WB_B64), *X = Wd(ctx, WB_Y), *R = Wd(ctx, WB_R64), *T64 = Wd(ctx, WB_T64),
             *Rt = Wd(ctx, WB_X);
-    double2 *V = Wd(ctx, WB_P0), *AV = Wd(ctx, WB_P1);
-    double2 *Pp = Wd(ctx, WB_Q0), *Pn = Wd(ctx, WB_Q1), *APp = Wd(ctx, WB_AP), *APn = Wd(ctx, WB_T);
-    double2 *Gv = M(ctx, M_G), *Gvv = M(ctx, M_H), *Ga = M(ctx, M_BETA), *Wpm = M(ctx, M_BETAC),
-            *Pv = M(ctx, M_C), *Bk = M(ctx, M_CINV), *alpha = M(ctx, M_SINV), *nalpha = M(ctx, M_SH);
+    double2 *PS = Wd(ctx, WB_P0), *APS = Wd(ctx, WB_P1);
+    double2 *Bk = M(ctx, M_CINV), *alpha = M(ctx, M_SINV), *nalpha = M(ctx, M_SH);
+    // K <= 32: two Hermitian Grams of U (2K <= 64 columns) hold every product as a
+    // block; above, five Grams of K columns
+    const bool wide = 2 * K <= MAXN;
+    double2 *GU = M(ctx, M_G), *GUU = M(ctx, M_H);
+    double2 *Gv5 = M(ctx, M_G), *Gvv5 = M(ctx, M_H), *Ga5 = M(ctx, M_BETA), *Wp5 = M(ctx, M_BETAC),
+            *Pv5 = M(ctx, M_C);
     int* d_status = ctx->d_flags + 1;
     double* d_rn = ctx->d_vec + 2 * MAXN;   // iterated residual norms
     double* d_lam = ctx->d_vec + 3 * MAXN;  // power-iteration estimate
@@ -1440,6 +1447,7 @@ int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_ste
     HIPCK(hipMemsetAsync(d_status, 0, sizeof(int), s));
     const int max_outer = std::max(1, ctx->max_iter / S);
     int status = BCG_OK, outer = 0, restarts = 0;
+    int pslot = -1;  // slot of P' (-1: none, the first outer iteration after a (re)start)
     bool first = true;
     double tr[MAXN];
     for (;;) {
@@ -1472,6 +1480,7 @@ int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_ste
             // restart the recurrence from the true residual
             HIPCK(launch_copy(Rt, R, n * 16, s));
             first = true;
+            pslot = -1;
             restarts += 1;
         }
         if (outer >= max_outer) {
@@ -1479,6 +1488,13 @@ int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_ste
             fail(ctx, status, "max_iter reached in s-step block CG");
             break;
         }
+        // slots: V next to P' (the middle slot unless P' is there), the new
+        // directions in the remaining one; the first directions are V itself
+        const int vslot = first ? 1 : (pslot == 1 ? 0 : 1);
+        const int nslot = first ? vslot : 3 - pslot - vslot;
+        double2 *V = PS + vslot * nK, *AV = APS + vslot * nK;
+        double2 *Pn = PS + nslot * nK, *APn = APS + nslot * nK;
+        double2 *Pp = first ? nullptr : PS + pslot * nK, *APp = first ? nullptr : APS + pslot * nK;
         // basis V = [R, p_1(A) R, ...] (Chebyshev polynomials of [lmin, lmax]) and AV = A V
         HIPCK(launch_copy(R, V, n * 16, s));
         for (int j = 0; j < S; ++j) {
@@ -1489,14 +1505,37 @@ int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_ste
                                        (j ? 2.0 : 1.0) / hh, cc, n, s));
             }
         }
-        // one reduction phase: the Hermitian V^H AV, V^H V, P'^H AP' on the matrix
-        // cores, the general (AP')^H V and P'^H V on the vector ALUs
-        RETCK(gram(ctx, Prec::FP64, V, AV, K, Gv, nullptr));
-        RETCK(gram(ctx, Prec::FP64, V, V, K, Gvv, nullptr));
-        if (!first) {
-            RETCK(gram_general(ctx, APp, V, K, Ga));
-            RETCK(gram(ctx, Prec::FP64, Pp, APp, K, Wpm, nullptr));
-            RETCK(gram_general(ctx, Pp, V, K, Pv));
+        // one reduction phase
+        const double2 *Gv, *Gvv, *Ga = nullptr, *Wpm = nullptr, *Pv = nullptr;
+        if (first) {
+            RETCK(gram(ctx, Prec::FP64, V, AV, K, Gv5, nullptr));
+            RETCK(gram(ctx, Prec::FP64, V, V, K, Gvv5, nullptr));
+            Gv = Gv5;
+            Gvv = Gvv5;
+        } else if (wide) {
+            // U^H A U and U^H U for U = the two adjacent slots of V and P'
+            const int lo = std::min(vslot, pslot);
+            const int vo = vslot < pslot ? 0 : K, po = K - vo;
+            RETCK(gram(ctx, Prec::FP64, PS + lo * nK, APS + lo * nK, 2 * K, GU, nullptr));
+            RETCK(gram(ctx, Prec::FP64, PS + lo * nK, PS + lo * nK, 2 * K, GUU, nullptr));
+            Gv = GU + vo * MAXN + vo;
+            Ga = GU + po * MAXN + vo;   // P'^H A V = (A P')^H V
+            Wpm = GU + po * MAXN + po;
+            Gvv = GUU + vo * MAXN + vo;
+            Pv = GUU + po * MAXN + vo;
+        } else {
+            // the Hermitian V^H AV, V^H V, P'^H AP' on the matrix cores, the general
+            // (AP')^H V and P'^H V on the vector ALUs
+            RETCK(gram(ctx, Prec::FP64, V, AV, K, Gv5, nullptr));
+            RETCK(gram(ctx, Prec::FP64, V, V, K, Gvv5, nullptr));
+            RETCK(gram_general(ctx, APp, V, K, Ga5));
+            RETCK(gram(ctx, Prec::FP64, Pp, APp, K, Wp5, nullptr));
+            RETCK(gram_general(ctx, Pp, V, K, Pv5));
+            Gv = Gv5;
+            Gvv = Gvv5;
+            Ga = Ga5;
+            Wpm = Wp5;
+            Pv = Pv5;
         }
         {
             Prof pr(ctx, BCG_K_SMALL);
@@ -1505,18 +1544,14 @@ int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_ste
         {
             // P = V + P' Bk, AP = AV + AP' Bk, X += P alpha, R -= AP alpha
             Prof pr(ctx, BCG_K_PASS_B);
-            if (first) {
-                HIPCK(launch_copy(V, Pn, (long)bK, s));
-                HIPCK(launch_copy(AV, APn, (long)bK, s));
-            } else {
+            if (!first) {
                 HIPCK(launch_bmul(Prec::FP64, Pp, Prec::FP64, V, Pn, Bk, K, Vh, d_status, s));
                 HIPCK(launch_bmul(Prec::FP64, APp, Prec::FP64, AV, APn, Bk, K, Vh, d_status, s));
             }
             HIPCK(launch_bmul_rect(Pn, X, X, alpha, K, N, Vh, d_status, s));
             HIPCK(launch_bmul_rect(APn, R, R, nalpha, K, N, Vh, d_status, s));
         }
-        std::swap(Pp, Pn);
-        std::swap(APp, APn);
+        pslot = nslot;
         first = false;
         outer += 1;
     }

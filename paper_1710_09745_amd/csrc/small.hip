@@ -762,7 +762,8 @@ k_small_qr2(const double2* __restrict__ H2, double2* __restrict__ Cacc, double2*
 // The inverses go through the Cholesky factor L and Z = L^{-1} (W^{-1} = Z^H Z).
 // A non-positive pivot of Wp (status 1) or W (status 2) stops the kernel with
 // *status set; the update kernels that follow take *status as their skip flag.
-// LDS holds two K x K matrices; every K^3 product reads LDS only, and its result
+// LDS holds two K x K matrices (four for K <= 32, where the Cholesky factorisations
+// take 2 x 2 pivots); every K^3 product reads LDS only, and its result
 // goes to a global [64][64] array (nalpha or alpha before they receive their final
 // values) and back into LDS after a barrier, which makes the workgroup's global
 // writes visible to all of its threads.
@@ -771,59 +772,83 @@ __device__ void load_full(Z2* A, const double2* M, int K) {
     for (int e = threadIdx.x; e < K * K; e += blockDim.x) A[e] = gld(M + gofs(e, K));
 }
 
+// LDS matrices of k_sstep_coef: four for K <= 32 (the 2 x 2-pivot ping-pong
+// Cholesky), two above
+__host__ __device__ constexpr int sstep_bufs(int K) { return K <= 32 ? 4 : 2; }
+
+// Cholesky W = L L^H of the Hermitian K x K matrix in b[0] and Z = L^{-1}: *Z gets
+// the buffer holding Z and *spare a buffer free for other use.  False on a
+// non-positive pivot (uniform over the workgroup).
+__device__ bool sstep_chol(Z2* const* b, int K, Z2* colk, Z2** Z, Z2** spare) {
+    if (sstep_bufs(K) == 4) {
+        bool ok = false;
+        Z2 *L = nullptr, *Zo = nullptr;
+        chol_inv_lower_pp(b[0], b[2], b[1], b[3], K, nullptr, ok, &L, &Zo);
+        *Z = Zo;
+        *spare = L;
+        return ok;
+    }
+    if (!chol_inv_lower(b[0], b[1], K, nullptr, colk)) return false;
+    *Z = b[1];
+    *spare = b[0];
+    return true;
+}
+
 __global__ void __launch_bounds__(1024)
 k_sstep_coef(const double2* __restrict__ Gv, const double2* __restrict__ Gvv, const double2* __restrict__ Ga,
              const double2* __restrict__ Wp, const double2* __restrict__ Pv, double2* __restrict__ Bk,
              double2* __restrict__ alpha, double2* __restrict__ nalpha, int* __restrict__ status, int K, int N,
              int first) {
     extern __shared__ Z2 sm[];
-    Z2* A = sm;
-    Z2* Zm = sm + K * K;
+    Z2* b[4];
+    for (int q = 0; q < 4; ++q) b[q] = sm + (q < sstep_bufs(K) ? q : 0) * K * K;
     __shared__ Z2 colk[MAXN];
+    Z2 *Zm = nullptr, *S = nullptr;
     if (!first) {
-        load_herm(A, Wp, K);
+        load_herm(b[0], Wp, K);
         __syncthreads();
-        if (!chol_inv_lower(A, Zm, K, nullptr, colk)) {
+        if (!sstep_chol(b, K, colk, &Zm, &S)) {
             if (threadIdx.x == 0) *status = 1;
             return;
         }
-        load_full(A, Ga, K);
+        load_full(S, Ga, K);
         __syncthreads();
         // Y = Z Ga (Z lower triangular) -> nalpha
         for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
             const int i = row_of(e, K), j = e - i * K;
             Z2 acc{0.0, 0.0};
             for (int l = 0; l <= i; ++l) {
-                const Z2 p = zmul(Zm[i * K + l], A[l * K + j]);
+                const Z2 p = zmul(Zm[i * K + l], S[l * K + j]);
                 acc.re += p.re;
                 acc.im += p.im;
             }
             gst(nalpha + i * MAXN + j, acc);
         }
         __syncthreads();
-        load_full(A, nalpha, K);
+        load_full(S, nalpha, K);
         __syncthreads();
         // Bk = -Z^H Y
         for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
             const int i = row_of(e, K), j = e - i * K;
             Z2 acc{0.0, 0.0};
             for (int l = i; l < K; ++l) {
-                const Z2 p = zmul(zconj(Zm[l * K + i]), A[l * K + j]);
+                const Z2 p = zmul(zconj(Zm[l * K + i]), S[l * K + j]);
                 acc.re += p.re;
                 acc.im += p.im;
             }
             gst(Bk + i * MAXN + j, Z2{-acc.re, -acc.im});
         }
         __syncthreads();
-        load_full(A, Ga, K);
-        load_full(Zm, Bk, K);
+        Z2 *GaL = S, *BkL = Zm;
+        load_full(GaL, Ga, K);
+        load_full(BkL, Bk, K);
         __syncthreads();
         // W = Gv + Ga^H Bk -> nalpha;  g = Gr + Bk^H Pr -> alpha
         for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
             const int i = row_of(e, K), j = e - i * K;
             Z2 acc = gld(Gv + i * MAXN + j);
             for (int l = 0; l < K; ++l) {
-                const Z2 p = zmul(zconj(A[l * K + i]), Zm[l * K + j]);
+                const Z2 p = zmul(zconj(GaL[l * K + i]), BkL[l * K + j]);
                 acc.re += p.re;
                 acc.im += p.im;
             }
@@ -833,16 +858,16 @@ k_sstep_coef(const double2* __restrict__ Gv, const double2* __restrict__ Gvv, co
             const int i = row_of(e, N), n = e - i * N;
             Z2 acc = gld(Gvv + i * MAXN + n);
             for (int l = 0; l < K; ++l) {
-                const Z2 p = zmul(zconj(Zm[l * K + i]), gld(Pv + l * MAXN + n));
+                const Z2 p = zmul(zconj(BkL[l * K + i]), gld(Pv + l * MAXN + n));
                 acc.re += p.re;
                 acc.im += p.im;
             }
             gst(alpha + i * MAXN + n, acc);
         }
         __syncthreads();
-        load_herm(A, nalpha, K);
+        load_herm(b[0], nalpha, K);
     } else {
-        load_herm(A, Gv, K);
+        load_herm(b[0], Gv, K);
         for (int e = threadIdx.x; e < K * K; e += blockDim.x) gst(Bk + gofs(e, K), Z2{0.0, 0.0});
         for (int e = threadIdx.x; e < K * N; e += blockDim.x) {
             const int i = row_of(e, N), n = e - i * N;
@@ -850,11 +875,11 @@ k_sstep_coef(const double2* __restrict__ Gv, const double2* __restrict__ Gvv, co
         }
     }
     __syncthreads();
-    if (!chol_inv_lower(A, Zm, K, nullptr, colk)) {
+    if (!sstep_chol(b, K, colk, &Zm, &S)) {
         if (threadIdx.x == 0) *status = 2;
         return;
     }
-    // T = Z g (into A, K x N with leading dimension N), then alpha = Z^H T
+    // T = Z g (into S, K x N with leading dimension N), then alpha = Z^H T
     for (int e = threadIdx.x; e < K * N; e += blockDim.x) {
         const int i = row_of(e, N), n = e - i * N;
         Z2 acc{0.0, 0.0};
@@ -863,14 +888,14 @@ k_sstep_coef(const double2* __restrict__ Gv, const double2* __restrict__ Gvv, co
             acc.re += p.re;
             acc.im += p.im;
         }
-        A[e] = acc;
+        S[e] = acc;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < K * N; e += blockDim.x) {
         const int i = row_of(e, N), n = e - i * N;
         Z2 acc{0.0, 0.0};
         for (int l = i; l < K; ++l) {
-            const Z2 p = zmul(zconj(Zm[l * K + i]), A[l * N + n]);
+            const Z2 p = zmul(zconj(Zm[l * K + i]), S[l * N + n]);
             acc.re += p.re;
             acc.im += p.im;
         }
@@ -920,8 +945,8 @@ hipError_t launch_sstep_coef(const double2* Gv, const double2* Gvv, const double
                              const double2* Pv, double2* Bk, double2* alpha, double2* nalpha, int* status, int K,
                              int N, int first, hipStream_t s) {
     if (K < 1 || K > MAXN || N < 1 || N > K) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_sstep_coef, dim3(1), dim3(small_threads(K, 0)), 2 * (size_t)K * K * sizeof(Z2), s, Gv, Gvv,
-                       Ga, Wp, Pv, Bk, alpha, nalpha, status, K, N, first);
+    hipLaunchKernelGGL(k_sstep_coef, dim3(1), dim3(small_threads(K, 0)), sstep_bufs(K) * (size_t)K * K * sizeof(Z2),
+                       s, Gv, Gvv, Ga, Wp, Pv, Bk, alpha, nalpha, status, K, N, first);
     return hipGetLastError();
 }
 hipError_t launch_small1(const double2* G, const double2* C, double2* beta, double2* betaC,

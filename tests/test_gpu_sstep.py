@@ -76,8 +76,9 @@ def test_solve_converges(dims, n, s):
     assert res.max() <= 1e-10
     assert np.allclose(res, info["true_rel_res"], rtol=1e-3, atol=1e-14)
     # the s-step space after k outer iterations is block CG's after k s iterations:
-    # it cannot stop much earlier, and rounding costs it at most a factor here
-    assert ib["iters"] - s <= info["iters"] <= 2.5 * ib["iters"]
+    # neither stops much earlier than the other in floating point (rounding delays
+    # both by a few per cent), and rounding costs the s-step form at most a factor
+    assert 0.9 * ib["iters"] - s <= info["iters"] <= 2.5 * ib["iters"]
     kappa = kappa_bound(op)
     assert col_rel_err(X.cpu().numpy(), Xb.cpu().numpy()).max() <= kappa * 2e-10
 
