@@ -160,6 +160,8 @@ def main():
     ap.add_argument("--tsm-eps", type=float, default=0.6, help="eps of the smooth links")
     ap.add_argument("--tsm-pseudo", action="store_true",
                     help="tsm192: also run pseudo-block CG at every block size > 1 (FP64 storage)")
+    ap.add_argument("--sstep", default="2,4",
+                    help="also time s-step block CG at these s (FP64 storage, comma list; '' = none)")
     ap.add_argument("--nrhs", type=int, default=16)
     ap.add_argument("--prec", default=None, help="storage precision override (fp64/fp32/fp16/bf16/fix16)")
     ap.add_argument("--no-cg", action="store_true")
@@ -292,6 +294,27 @@ def main():
         print(f"[bench] pseudo-block {pb_ms:.2f} ms for {N} columns ({ipb['iters']} lockstep iters)",
               file=sys.stderr, flush=True)
 
+    # s-step block CG (FP64): s block directions per outer iteration, one reduction
+    # phase per outer iteration instead of two per iteration
+    sstep = []
+    if prec == "fp64" and args.sstep:
+        for sv in [int(x) for x in args.sstep.split(",") if x.strip()]:
+            if sv * N > 64:
+                continue
+            ctx.set_monitor(Progress(f"s-step s={sv}"))
+            _, iss = ctx.solve_sstep(Bt, sv)      # warm (and the library's spectrum estimate)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            for _ in range(args.cg_steps):
+                _, iss = ctx.solve_sstep(Bt, sv)
+            torch.cuda.synchronize()
+            ss_ms = (time.perf_counter() - t3) * 1e3 / args.cg_steps
+            sstep.append({"s": sv, "ms_per_rhs": round(ss_ms / N, 4), "steps": iss["iters"],
+                          "restarts": iss["restarts"], "max_true_rel_res": iss["max_true_rel_res"],
+                          "us_per_step": round(ss_ms / max(iss["iters"], 1) * 1e3, 1)})
+            print(f"[bench] s-step s={sv}: {ss_ms:.2f} ms for {N} columns ({iss['iters']} steps)",
+                  file=sys.stderr, flush=True)
+
     # roofline of the dominant kernel
     Vh = synth.volume(dims) // 2
     per_site = model_bytes_per_site(dominant, N, prec)
@@ -348,6 +371,7 @@ def main():
         "pseudo_block_iters": ipb["iters"] if ipb else None,
         "speedup_link_reuse": round(cg_ms / pb_ms, 3) if (pb_ms and cg_ms) else None,
         "speedup_krylov_sharing": round(pb_ms / ms_per_step, 3) if pb_ms else None,
+        "sstep": sstep or None,
         "cg_fp64_ms_per_rhs": round(cg64_ms / N, 4) if cg64_ms else None,
         "speedup_vs_cg_fp64": round(cg64_ms / ms_per_step, 3) if cg64_ms else None,
         "roofline": roofline,
