@@ -1750,16 +1750,23 @@ hipError_t launch_colnorm2(const double2* V, int N, int Vh, double* partials, hi
     return hipGetLastError();
 }
 
-__global__ void k_colnorm_reduce(const double* __restrict__ partials, int N, int P, double* __restrict__ out, int take_sqrt) {
-    const int j = threadIdx.x;
-    if (j >= N) return;
-    double s = 0.0;
-    for (int b = 0; b < P; ++b) s += partials[(long)b * N + j];
-    out[j] = take_sqrt ? sqrt(s) : s;
+// out[j] = sum_b partials[b*N + j] (its square root if take_sqrt): one wave per
+// column, lanes strided over the partials, then a fixed butterfly (deterministic)
+__global__ void __launch_bounds__(1024)
+k_colnorm_reduce(const double* __restrict__ partials, int N, int P, double* __restrict__ out, int take_sqrt) {
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int j = wave; j < N; j += nw) {
+        double s = 0.0;
+        for (int b = lane; b < P; b += 64) s += partials[(long)b * N + j];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) out[j] = take_sqrt ? sqrt(s) : s;
+    }
 }
 hipError_t launch_colnorm_reduce(const double* partials, int N, int Vh, double* out, int take_sqrt,
                                  hipStream_t s) {
-    hipLaunchKernelGGL(k_colnorm_reduce, dim3(1), dim3(64), 0, s, partials, N, norm_blocks(Vh), out,
+    const int waves = N < 16 ? N : 16;
+    hipLaunchKernelGGL(k_colnorm_reduce, dim3(1), dim3(64 * waves), 0, s, partials, N, norm_blocks(Vh), out,
                        take_sqrt);
     return hipGetLastError();
 }

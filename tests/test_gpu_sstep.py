@@ -99,3 +99,22 @@ def test_deterministic(prob):
     X2, i2 = ctx.solve_sstep(to_dev(B[:8]), 3)
     assert i1["iters"] == i2["iters"]
     assert np.array_equal(X1.cpu().numpy(), X2.cpu().numpy())
+
+
+def test_restart_from_true_residual():
+    """At tol 1e-14 the iterated residual passes tol before the true one can: the
+    true-residual check restarts the recurrence (as in the oracle's pin on the same
+    4^4 problem), and the solve ends within a few ulps of the attainable accuracy."""
+    dims = (4, 4, 4, 4)
+    fat, lng, B = inputs(dims, False, 4, 7300)
+    ctx = context(dims, False, fat, lng, 0.1, tol=1e-14, max_iter=400)
+    print("[case] s-step restart s=2 n=4 tol=1e-14", flush=True)
+    X, info = ctx.solve_sstep(to_dev(B), 2, raise_on_error=False)
+    op = oracle.Operator(dims, fat, lng, 0.1)
+    res = true_rel_res(op, B, X.cpu().numpy())
+    print(f"s-step restarts {info['restarts']}, rc {info['rc']}, steps {info['iters']}, max res {res.max():.2e}")
+    assert info["restarts"] >= 1
+    assert info["rc"] in (bcg.OK, bcg.ERR_NOT_CONVERGED)
+    assert res.max() <= 5e-14
+    if info["rc"] == bcg.OK:
+        assert res.max() <= 1.01e-14
