@@ -334,7 +334,8 @@ def block_cg_rq(apply_A, B, tol, max_iter=100000, X0=None, ru_delta=0.0, sloppy=
     return from_mat(Y, vh), info
 
 
-def sstep_block_cg(apply_A, B, s, tol, lam, max_outer=100000, basis="chebyshev", trace=None):
+def sstep_block_cg(apply_A, B, s, tol, lam, max_outer=100000, basis="chebyshev", trace=None,
+                   sloppy=None, apply_sloppy=None, ru_delta=0.0):
     """s-step block CG: every outer iteration extends the search space by s block
     Krylov directions at once, so that all of its inner products form one
     reduction phase per s steps instead of two per step -- the s-step methods that
@@ -367,8 +368,16 @@ def sstep_block_cg(apply_A, B, s, tol, lam, max_outer=100000, basis="chebyshev",
     max_outer bounds the outer iterations.
     trace: optional list; per outer iteration a dict with Bk, W and alpha.
 
+    Low-precision storage (Sec. 6's mixed precision carried over): sloppy rounds
+    the stored block vectors V, AV, P and AP (each as formed, V_0 = R rounded) and
+    apply_sloppy is the operator of the basis; X, R, the Grams and all N x N work
+    stay FP64.  ru_delta > 0 adds reliable updates (Alg. 3's role): when the
+    maximum relative iterated residual has dropped by ru_delta since the last one,
+    R is replaced by the FP64 true residual B - A X and the directions P, AP are
+    kept (the reduced Pr = P^H R absorbs the change).
+
     Returns (X [N][V/2][3], SolveInfo(iters = outer iterations * s, outer,
-    restarts, converged, true_rel_res)).
+    restarts, reliable_updates, converged, true_rel_res)).
     Raises Breakdown when Wp or W is not positive definite.
     """
     B = np.asarray(B, dtype=np.complex128)
@@ -379,6 +388,8 @@ def sstep_block_cg(apply_A, B, s, tol, lam, max_outer=100000, basis="chebyshev",
     def A(M):
         return to_mat(apply_A(from_mat(M, vh)))
 
+    rnd = sloppy if sloppy is not None else (lambda a: a)
+    As = A if apply_sloppy is None else (lambda M: to_mat(apply_sloppy(from_mat(M, vh))))
     lmin, lmax = float(lam[0]), float(lam[1])
     c, h = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
     Bm = to_mat(B)
@@ -388,11 +399,13 @@ def sstep_block_cg(apply_A, B, s, tol, lam, max_outer=100000, basis="chebyshev",
     X = np.zeros_like(Bm)
     R = Bm.copy()
     P = AP = None
-    outer = restarts = 0
+    outer = restarts = n_ru = 0
     converged = False
     true_rel = np.linalg.norm(R, axis=0) / bnorm
+    rho_ru = float(true_rel.max())
     while True:
-        if np.max(np.linalg.norm(R, axis=0) / bnorm) <= tol:
+        relres = np.max(np.linalg.norm(R, axis=0) / bnorm)
+        if relres <= tol:
             Rt = Bm - A(X)
             true_rel = np.linalg.norm(Rt, axis=0) / bnorm
             if true_rel.max() <= tol:
@@ -400,32 +413,37 @@ def sstep_block_cg(apply_A, B, s, tol, lam, max_outer=100000, basis="chebyshev",
                 break
             R, P, AP = Rt, None, None
             restarts += 1
+            rho_ru = float(true_rel.max())
+        elif ru_delta > 0 and relres <= ru_delta * rho_ru:
+            R = Bm - A(X)
+            rho_ru = float(np.max(np.linalg.norm(R, axis=0) / bnorm))
+            n_ru += 1
         if outer >= max_outer:
             break
         # the s basis blocks and their images under A
-        Vb, AVb = [R], []
+        Vb, AVb = [rnd(R)], []
         for j in range(s):
-            AVb.append(A(Vb[j]))
+            AVb.append(rnd(As(Vb[j])))
             if j + 1 < s:
                 if basis == "monomial":
                     Vb.append(AVb[j])
                 elif j == 0:
-                    Vb.append((AVb[0] - c * Vb[0]) / h)
+                    Vb.append(rnd((AVb[0] - c * Vb[0]) / h))
                 else:
-                    Vb.append(2.0 * (AVb[j] - c * Vb[j]) / h - Vb[j - 1])
+                    Vb.append(rnd(2.0 * (AVb[j] - c * Vb[j]) / h - Vb[j - 1]))
         V, AV = np.hstack(Vb), np.hstack(AVb)
         Gv = V.conj().T @ AV
-        Gr = V.conj().T @ R
+        Gr = V.conj().T @ Vb[0]
         if P is None:
             Bk = np.zeros((s * n, s * n), dtype=np.complex128)
             P, AP, W, g = V, AV, Gv, Gr
         else:
             Ga = AP.conj().T @ V
             Wp = P.conj().T @ AP
-            Pr = P.conj().T @ R
+            Pr = P.conj().T @ Vb[0]
             Bk = -hpd_inverse(0.5 * (Wp + Wp.conj().T)) @ Ga
-            P = V + P @ Bk
-            AP = AV + AP @ Bk
+            P = rnd(V + P @ Bk)
+            AP = rnd(AV + AP @ Bk)
             W = Gv + Ga.conj().T @ Bk
             g = Gr + Bk.conj().T @ Pr
         W = 0.5 * (W + W.conj().T)
@@ -437,8 +455,8 @@ def sstep_block_cg(apply_A, B, s, tol, lam, max_outer=100000, basis="chebyshev",
             trace.append(dict(Bk=Bk, W=W, alpha=alpha))
     if not converged:
         true_rel = np.linalg.norm(Bm - A(X), axis=0) / bnorm
-    info = SolveInfo(iters=outer * s, outer=outer, restarts=restarts, converged=converged,
-                     true_rel_res=true_rel)
+    info = SolveInfo(iters=outer * s, outer=outer, restarts=restarts, reliable_updates=n_ru,
+                     converged=converged, true_rel_res=true_rel)
     return from_mat(X, vh), info
 
 

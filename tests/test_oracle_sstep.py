@@ -127,3 +127,54 @@ def test_zero_column_and_bad_s(p1):
         oracle.sstep_block_cg(op.apply, Bz, 2, 1e-10, lam)
     with pytest.raises(ValueError):
         oracle.sstep_block_cg(op.apply, B, 0, 1e-10, lam)
+
+
+def _fp32_storage(op):
+    """The emulated FP32 storage of the solver's sloppy path: links, the apply's
+    input, its odd-parity intermediate and its output rounded to binary32."""
+    from oracle import rounding
+    lng = rounding.round_links(op.lng, "fp32") if op.improved else None
+    ops = oracle.Operator(tuple(int(d) for d in op.dims), rounding.round_links(op.fat, "fp32"), lng, op.mass)
+
+    def apply_sloppy(v):
+        P = rounding.round_groups(v, "fp32", 1)
+        T = rounding.round_groups(ops.hop(1, P), "fp32", 1)
+        return rounding.round_groups(4 * op.mass * op.mass * P - ops.hop(0, T), "fp32", 1)
+
+    return rounding.vector_rounder("fp32", op.Vh), apply_sloppy
+
+
+def test_reliable_update_is_a_no_op_in_fp64(p1):
+    """R replaced by B - A X at (almost) every outer iteration: in exact arithmetic the
+    replacement is the identity, so the iterates agree with the plain recurrence's."""
+    op, B, Ad, lam = p1
+    for s in (1, 3):
+        ref, _ = oracle.sstep_block_cg(op.apply, B, s, 1e-14, lam, max_outer=6)
+        X, info = oracle.sstep_block_cg(op.apply, B, s, 1e-14, lam, max_outer=6, ru_delta=0.9999)
+        assert info.reliable_updates >= 1
+        assert np.linalg.norm(oracle.to_mat(X - ref)) <= 1e-10 * np.linalg.norm(oracle.to_mat(ref))
+
+
+@pytest.mark.parametrize("improved,n,m,s", [(False, 4, 0.1, 1), (False, 4, 0.1, 2), (False, 4, 0.1, 4),
+                                             (True, 4, 0.05, 1), (True, 4, 0.05, 2)])
+def test_fp32_storage_with_reliable_updates(improved, n, m, s):
+    """FP32 storage of V, AV, P, AP and FP32 links in the basis: with reliable updates
+    every 10x drop the solve reaches 1e-8 by the FP64 operator without a restart.  It
+    needs more steps than blockCGrQ in the same storage (the s-step recurrence works on
+    the raw residual block, not on an orthonormal one: 1.0-1.2x on the naive operator,
+    1.3x at s = 1 and 1.7x at s = 2 on the improved one), and fewer than the same solve
+    without reliable updates, whose iterated residual drifts from the true one until a
+    restart is needed."""
+    op, B = problem(improved=improved, n=n, m=m, seed=31)
+    Ad = dense_A(op)
+    lam = spectrum(Ad)
+    rnd, As = _fp32_storage(op)
+    X, info = oracle.sstep_block_cg(op.apply, B, s, 1e-8, lam, max_outer=2000 // s, sloppy=rnd,
+                                    apply_sloppy=As, ru_delta=0.1)
+    assert info.converged and info.restarts == 0 and info.reliable_updates >= 1
+    r = np.linalg.norm(oracle.to_mat(B) - Ad @ oracle.to_mat(X), axis=0) / np.linalg.norm(oracle.to_mat(B), axis=0)
+    assert r.max() <= 1e-8
+    _, ib = oracle.block_cg_rq(op.apply, B, 1e-8, ru_delta=0.1, sloppy=rnd, apply_sloppy=As)
+    assert info.iters <= 1.8 * ib.iters + s
+    _, i0 = oracle.sstep_block_cg(op.apply, B, s, 1e-8, lam, max_outer=2000 // s, sloppy=rnd, apply_sloppy=As)
+    assert i0.restarts >= 1 and i0.iters > info.iters
