@@ -294,10 +294,11 @@ def main():
         print(f"[bench] pseudo-block {pb_ms:.2f} ms for {N} columns ({ipb['iters']} lockstep iters)",
               file=sys.stderr, flush=True)
 
-    # s-step block CG (FP64): s block directions per outer iteration, one reduction
-    # phase per outer iteration instead of two per iteration
+    # s-step block CG (FP64, or FP32 storage with reliable updates): s block
+    # directions per outer iteration, one reduction phase per outer iteration
+    # instead of two per iteration
     sstep = []
-    if prec == "fp64" and args.sstep:
+    if prec in ("fp64", "fp32") and args.sstep:
         for sv in [int(x) for x in args.sstep.split(",") if x.strip()]:
             if sv * N > 64:
                 continue
@@ -310,7 +311,8 @@ def main():
             torch.cuda.synchronize()
             ss_ms = (time.perf_counter() - t3) * 1e3 / args.cg_steps
             sstep.append({"s": sv, "ms_per_rhs": round(ss_ms / N, 4), "steps": iss["iters"],
-                          "restarts": iss["restarts"], "max_true_rel_res": iss["max_true_rel_res"],
+                          "restarts": iss["restarts"], "reliable_updates": iss["reliable_updates"],
+                          "max_true_rel_res": iss["max_true_rel_res"],
                           "us_per_step": round(ss_ms / max(iss["iters"], 1) * 1e3, 1)})
             print(f"[bench] s-step s={sv}: {ss_ms:.2f} ms for {N} columns ({iss['iters']} steps)",
                   file=sys.stderr, flush=True)

@@ -201,9 +201,15 @@ int bcg_solve_pseudo(bcg_ctx *ctx, const void *B, void *X, int nrhs, bcg_stats *
  * basis loses conditioning as s grows and the iteration count rises.  The
  * iterated residual is tested at the top of each outer iteration; when it meets
  * tol the FP64 true residual is checked and, if a column misses, the recurrence
- * restarts from the true residual.  FP64 storage and arithmetic regardless of
- * bcg_set_solver's sloppy_prec; tol and max_iter (counted in s-steps, rounded
- * down to whole outer iterations) come from bcg_set_solver.
+ * restarts from the true residual.  Storage follows bcg_set_solver's
+ * sloppy_prec: FP64, or FP32 (the mixed precision of Sec. 6 carried over: V,
+ * A V, P and A P stored in FP32 and the basis applied with the FP32 links in
+ * FP32 arithmetic, while X, R, every Gram and the coefficients stay FP64, and a
+ * reliable update replaces R by the FP64 true residual B - A X whenever the
+ * largest iterated relative residual has dropped by ru_delta since the last
+ * one, keeping the directions); 16-bit storage returns BCG_ERR_ARG.  tol,
+ * max_iter (counted in s-steps, rounded down to whole outer iterations) and
+ * ru_delta come from bcg_set_solver.
  *   s:    directions per outer iteration; s * nrhs <= 64 (BCG_ERR_ARG otherwise)
  *   lmin: lower end of the basis interval; <= 0 selects 4 m^2, the smallest
  *         possible eigenvalue of A
@@ -211,7 +217,7 @@ int bcg_solve_pseudo(bcg_ctx *ctx, const void *B, void *X, int nrhs, bcg_stats *
  *         of the largest eigenvalue from the first column (lmin < lmax required
  *         when both are given)
  * stats->iters counts s-steps (outer iterations times s), stats->restarts the
- * true-residual restarts.  Returns BCG_OK, BCG_ERR_NOT_CONVERGED or
+ * true-residual restarts, stats->reliable_updates the reliable updates.  Returns BCG_OK, BCG_ERR_NOT_CONVERGED or
  * BCG_ERR_BREAKDOWN (a direction Gram P^H A P not positive definite: the basis
  * lost rank; X holds the last iterate), or an argument / runtime error.  Same
  * vector arguments as bcg_solve with X0 = 0. */

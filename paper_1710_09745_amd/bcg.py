@@ -285,7 +285,9 @@ class Context:
     def solve_sstep(self, B, s, lmin=0.0, lmax=0.0, raise_on_error=True):
         """s-step block CG with s block directions per outer iteration (s * N <= 64)
         and a Chebyshev basis on [lmin, lmax] (<= 0: 4 m^2, and 1.1 times a
-        power-iteration estimate).  Returns (X, info); info["iters"] counts s-steps."""
+        power-iteration estimate), in the storage precision set by set_solver (fp64 or
+        fp32; fp32 adds reliable updates).  Returns (X, info); info["iters"] counts
+        s-steps."""
         _vec(B, "B", vh=self.Vh)
         X = torch.empty_like(B)
         rc, info = self._solve(self.lib.bcg_solve_sstep, B, X, int(s), float(lmin), float(lmax))

@@ -295,10 +295,10 @@ int gram(bcg_ctx* ctx, Prec p, const void* A, const void* B, int N, double2* out
 }
 
 // out = A^H B for any A, B (the vector-ALU Gram, which forms every tile)
-int gram_general(bcg_ctx* ctx, const double2* A, const double2* B, int N, double2* out) {
+int gram_general(bcg_ctx* ctx, Prec p, const void* A, const void* B, int N, double2* out) {
     {
         Prof pr(ctx, BCG_K_GRAM);
-        HIPCK(launch_gram(Prec::FP64, A, B, N, (int)ctx->Vh, ctx->partials, nullptr, false, ctx->stream));
+        HIPCK(launch_gram(p, A, B, N, (int)ctx->Vh, ctx->partials, nullptr, false, ctx->stream));
     }
     return reduce(ctx, ctx->partials, gram_parts(N, (int)ctx->Vh, false), nullptr, 0, 0.0, N, out, nullptr);
 }
@@ -1386,20 +1386,30 @@ int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_ste
         return fail(ctx, BCG_ERR_ARG, "s * nrhs must be in [1, 64], got s = " + std::to_string(s_steps));
     if (!std::isfinite(lmin) || !std::isfinite(lmax) || (lmax > 0.0 && lmin >= lmax))
         return fail(ctx, BCG_ERR_ARG, "the basis interval needs finite lmin < lmax");
+    // storage of V, AV, P and AP: FP64, or FP32 with FP64 reliable updates (16-bit
+    // storage keeps one scale array after all columns of a block, so the sub-blocks
+    // of the basis would not be blocks of their own)
+    const Prec ps = ctx->sloppy;
+    if (ps != Prec::FP64 && ps != Prec::FP32)
+        return fail(ctx, BCG_ERR_ARG, "the s-step solver stores its blocks in FP64 or FP32");
     const auto t0 = std::chrono::steady_clock::now();
     const int N = nrhs, S = s_steps, K = S * N;
     const int Vh = (int)ctx->Vh;
     const long n = nvec(ctx, N), n1 = 3L * Vh;
     hipStream_t s = ctx->stream;
-    RETCK(alloc_solve(ctx, N, Prec::FP64));
+    RETCK(alloc_solve(ctx, N, ps));
+    RETCK(ensure_sloppy_links(ctx, ps));
     // three slots of K columns for the basis V, the previous directions P' and the
     // new ones (and the same for AV, AP', AP): V always sits next to P', so that
     // U = [V | P'] (or [P' | V]) is one block of 2K columns
     const long nK = nvec(ctx, K);
-    for (int slot : {WB_P0, WB_P1}) RETCK(ensure(ctx, slot, (size_t)3 * nK * 16));
+    const size_t eb = ps == Prec::FP64 ? 16 : 8;  // bytes per stored complex entry
+    for (int slot : {WB_P0, WB_P1}) RETCK(ensure(ctx, slot, (size_t)3 * nK * eb));
     double2 *B64 = Wd(ctx, WB_B64), *X = Wd(ctx, WB_Y), *R = Wd(ctx, WB_R64), *T64 = Wd(ctx, WB_T64),
             *Rt = Wd(ctx, WB_X);
-    double2 *PS = Wd(ctx, WB_P0), *APS = Wd(ctx, WB_P1);
+    char *PS = (char*)W(ctx, WB_P0), *APS = (char*)W(ctx, WB_P1);
+    void* Ts = W(ctx, WB_T);  // odd-parity scratch of the stored-precision apply
+    auto at = [&](char* base, long pairs) -> char* { return base + (size_t)pairs * eb; };
     double2 *Bk = M(ctx, M_CINV), *alpha = M(ctx, M_SINV), *nalpha = M(ctx, M_SH);
     // K <= 32: two Hermitian Grams of U (2K <= 64 columns) hold every product as a
     // block; above, five Grams of K columns
@@ -1445,8 +1455,13 @@ int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_ste
     HIPCK(launch_zero(X, n * 16, s));
     HIPCK(launch_copy(B64, R, n * 16, s));
     HIPCK(hipMemsetAsync(d_status, 0, sizeof(int), s));
+    if (ps != Prec::FP64) HIPCK(launch_identity(M(ctx, M_ID), N, s));
     const int max_outer = std::max(1, ctx->max_iter / S);
-    int status = BCG_OK, outer = 0, restarts = 0;
+    // reliable updates (FP32 storage): R <- B - A X in FP64 whenever the largest
+    // iterated relative residual has dropped by ru_delta since the last one
+    const double ru_delta = ps == Prec::FP64 ? 0.0 : ctx->ru_delta;
+    double rho_ru = 1.0;
+    int status = BCG_OK, outer = 0, restarts = 0, rus = 0;
     int pslot = -1;  // slot of P' (-1: none, the first outer iteration after a (re)start)
     bool first = true;
     double tr[MAXN];
@@ -1482,6 +1497,18 @@ int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_ste
             first = true;
             pslot = -1;
             restarts += 1;
+            rho_ru = tm;
+        } else if (ru_delta > 0.0 && mx <= ru_delta * rho_ru) {
+            // reliable update: the directions P', AP' are kept; the reduced products
+            // with the new residual enter through P'^H V and V^H V
+            RETCK(apply64(ctx, X, R, T64, N, nullptr));
+            HIPCK(launch_residual(B64, R, n, s));
+            RETCK(colnorms(ctx, R, N, d_rn));
+            HIPCK(hipMemcpyAsync(ctx->h_vec, d_rn, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+            RETCK(sync(ctx));
+            rho_ru = 0.0;
+            for (int i = 0; i < N; ++i) rho_ru = std::fmax(rho_ru, ctx->h_vec[i] / bn[i]);
+            rus += 1;
         }
         if (outer >= max_outer) {
             status = BCG_ERR_NOT_CONVERGED;
@@ -1492,32 +1519,43 @@ int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_ste
         // directions in the remaining one; the first directions are V itself
         const int vslot = first ? 1 : (pslot == 1 ? 0 : 1);
         const int nslot = first ? vslot : 3 - pslot - vslot;
-        double2 *V = PS + vslot * nK, *AV = APS + vslot * nK;
-        double2 *Pn = PS + nslot * nK, *APn = APS + nslot * nK;
-        double2 *Pp = first ? nullptr : PS + pslot * nK, *APp = first ? nullptr : APS + pslot * nK;
-        // basis V = [R, p_1(A) R, ...] (Chebyshev polynomials of [lmin, lmax]) and AV = A V
-        HIPCK(launch_copy(R, V, n * 16, s));
+        char *V = at(PS, vslot * nK), *AV = at(APS, vslot * nK);
+        char *Pn = at(PS, nslot * nK), *APn = at(APS, nslot * nK);
+        char *Pp = first ? nullptr : at(PS, pslot * nK), *APp = first ? nullptr : at(APS, pslot * nK);
+        // basis V = [R, p_1(A) R, ...] (Chebyshev polynomials of [lmin, lmax]) and AV = A V,
+        // each block rounded to the storage precision as it is formed
+        if (ps == Prec::FP64) {
+            HIPCK(launch_copy(R, V, n * 16, s));
+        } else {
+            Prof pr(ctx, BCG_K_CONVERT);
+            HIPCK(launch_bmul(Prec::FP64, R, ps, nullptr, V, M(ctx, M_ID), N, Vh, nullptr, s));
+        }
         for (int j = 0; j < S; ++j) {
-            RETCK(apply64(ctx, V + j * n, AV + j * n, T64, N, nullptr));
+            if (ps == Prec::FP64) {
+                RETCK(apply64(ctx, at(V, j * n), at(AV, j * n), T64, N, nullptr));
+            } else {
+                RETCK(hop(ctx, ps, 1, at(V, j * n), Ts, nullptr, N, EPI_PLAIN_, nullptr));
+                RETCK(hop(ctx, ps, 0, Ts, at(AV, j * n), at(V, j * n), N, EPI_MASS_, nullptr));
+            }
             if (j + 1 < S) {
                 Prof pr(ctx, BCG_K_OTHER);
-                HIPCK(launch_cheb_step(V + (j + 1) * n, AV + j * n, V + j * n, j ? V + (j - 1) * n : nullptr,
-                                       (j ? 2.0 : 1.0) / hh, cc, n, s));
+                HIPCK(launch_cheb_step(ps, at(V, (j + 1) * n), at(AV, j * n), at(V, j * n),
+                                       j ? at(V, (j - 1) * n) : nullptr, (j ? 2.0 : 1.0) / hh, cc, n, s));
             }
         }
         // one reduction phase
         const double2 *Gv, *Gvv, *Ga = nullptr, *Wpm = nullptr, *Pv = nullptr;
         if (first) {
-            RETCK(gram(ctx, Prec::FP64, V, AV, K, Gv5, nullptr));
-            RETCK(gram(ctx, Prec::FP64, V, V, K, Gvv5, nullptr));
+            RETCK(gram(ctx, ps, V, AV, K, Gv5, nullptr));
+            RETCK(gram(ctx, ps, V, V, K, Gvv5, nullptr));
             Gv = Gv5;
             Gvv = Gvv5;
         } else if (wide) {
             // U^H A U and U^H U for U = the two adjacent slots of V and P'
             const int lo = std::min(vslot, pslot);
             const int vo = vslot < pslot ? 0 : K, po = K - vo;
-            RETCK(gram(ctx, Prec::FP64, PS + lo * nK, APS + lo * nK, 2 * K, GU, nullptr));
-            RETCK(gram(ctx, Prec::FP64, PS + lo * nK, PS + lo * nK, 2 * K, GUU, nullptr));
+            RETCK(gram(ctx, ps, at(PS, lo * nK), at(APS, lo * nK), 2 * K, GU, nullptr));
+            RETCK(gram(ctx, ps, at(PS, lo * nK), at(PS, lo * nK), 2 * K, GUU, nullptr));
             Gv = GU + vo * MAXN + vo;
             Ga = GU + po * MAXN + vo;   // P'^H A V = (A P')^H V
             Wpm = GU + po * MAXN + po;
@@ -1526,11 +1564,11 @@ int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_ste
         } else {
             // the Hermitian V^H AV, V^H V, P'^H AP' on the matrix cores, the general
             // (AP')^H V and P'^H V on the vector ALUs
-            RETCK(gram(ctx, Prec::FP64, V, AV, K, Gv5, nullptr));
-            RETCK(gram(ctx, Prec::FP64, V, V, K, Gvv5, nullptr));
-            RETCK(gram_general(ctx, APp, V, K, Ga5));
-            RETCK(gram(ctx, Prec::FP64, Pp, APp, K, Wp5, nullptr));
-            RETCK(gram_general(ctx, Pp, V, K, Pv5));
+            RETCK(gram(ctx, ps, V, AV, K, Gv5, nullptr));
+            RETCK(gram(ctx, ps, V, V, K, Gvv5, nullptr));
+            RETCK(gram_general(ctx, ps, APp, V, K, Ga5));
+            RETCK(gram(ctx, ps, Pp, APp, K, Wp5, nullptr));
+            RETCK(gram_general(ctx, ps, Pp, V, K, Pv5));
             Gv = Gv5;
             Gvv = Gvv5;
             Ga = Ga5;
@@ -1545,11 +1583,11 @@ int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_ste
             // P = V + P' Bk, AP = AV + AP' Bk, X += P alpha, R -= AP alpha
             Prof pr(ctx, BCG_K_PASS_B);
             if (!first) {
-                HIPCK(launch_bmul(Prec::FP64, Pp, Prec::FP64, V, Pn, Bk, K, Vh, d_status, s));
-                HIPCK(launch_bmul(Prec::FP64, APp, Prec::FP64, AV, APn, Bk, K, Vh, d_status, s));
+                HIPCK(launch_bmul(ps, Pp, ps, V, Pn, Bk, K, Vh, d_status, s));
+                HIPCK(launch_bmul(ps, APp, ps, AV, APn, Bk, K, Vh, d_status, s));
             }
-            HIPCK(launch_bmul_rect(Pn, X, X, alpha, K, N, Vh, d_status, s));
-            HIPCK(launch_bmul_rect(APn, R, R, nalpha, K, N, Vh, d_status, s));
+            HIPCK(launch_bmul_rect(ps, Pn, X, X, alpha, K, N, Vh, d_status, s));
+            HIPCK(launch_bmul_rect(ps, APn, R, R, nalpha, K, N, Vh, d_status, s));
         }
         pslot = nslot;
         first = false;
@@ -1569,7 +1607,7 @@ int bcg_solve_sstep(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, int s_ste
     if (status != BCG_OK)
         for (int i = 0; i < N; ++i) tr[i] = ctx->h_vec[i] / bn[i];
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    fill_stats(stats, outer * S, 0, status, restarts, secs, tr, N);
+    fill_stats(stats, outer * S, rus, status, restarts, secs, tr, N);
     return status;
 }
 

@@ -1584,9 +1584,13 @@ static hipError_t bmul_y(Prec py, const void* X, const void* Z, void* Y, const d
     return hipGetLastError();
 }
 
-hipError_t launch_bmul_rect(const double2* X, const double2* Z, double2* Y, const double2* M, int Nin, int Nout,
-                            int Vh, const int* skip, hipStream_t s) {
-    bmul_t<F64, F64>(X, Z, Y, M, Nin, Nout, Vh, skip, s);
+hipError_t launch_bmul_rect(Prec px, const void* X, const double2* Z, double2* Y, const double2* M, int Nin,
+                            int Nout, int Vh, const int* skip, hipStream_t s) {
+    switch (px) {
+        case Prec::FP64: bmul_t<F64, F64>(X, Z, Y, M, Nin, Nout, Vh, skip, s); break;
+        case Prec::FP32: bmul_t<F32, F64>(X, Z, Y, M, Nin, Nout, Vh, skip, s); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1688,24 +1692,36 @@ hipError_t launch_copy(const void* src, void* dst, long bytes, hipStream_t s) {
 }
 
 // One step of the Chebyshev basis of the s-step solver:
-// Vn = a (AV - c V) - Vm  (Vm may be NULL = 0), FP64 pairs, n entries
-__global__ void __launch_bounds__(256) k_cheb_step(double2* __restrict__ Vn, const double2* __restrict__ AV,
-                                                   const double2* __restrict__ V, const double2* __restrict__ Vm,
+// Vn = a (AV - c V) - Vm  (Vm may be NULL = 0), n complex entries of FP64 or FP32
+// storage, formed in FP64 and rounded once on the store
+template <typename P>
+__global__ void __launch_bounds__(256) k_cheb_step(P* __restrict__ Vn, const P* __restrict__ AV,
+                                                   const P* __restrict__ V, const P* __restrict__ Vm,
                                                    double a, double c, long n) {
     for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-        const double2 av = AV[t], v = V[t];
-        double2 r = make_double2(a * (av.x - c * v.x), a * (av.y - c * v.y));
+        const P av = AV[t], v = V[t];
+        double rx = a * ((double)av.x - c * (double)v.x), ry = a * ((double)av.y - c * (double)v.y);
         if (Vm != nullptr) {
-            const double2 m = Vm[t];
-            r.x -= m.x;
-            r.y -= m.y;
+            const P m = Vm[t];
+            rx -= (double)m.x;
+            ry -= (double)m.y;
         }
+        P r;
+        r.x = rx;
+        r.y = ry;
         Vn[t] = r;
     }
 }
-hipError_t launch_cheb_step(double2* Vn, const double2* AV, const double2* V, const double2* Vm, double a, double c,
+hipError_t launch_cheb_step(Prec p, void* Vn, const void* AV, const void* V, const void* Vm, double a, double c,
                             long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_cheb_step, dim3(stream_grid(n)), dim3(256), 0, s, Vn, AV, V, Vm, a, c, n);
+    if (p == Prec::FP64)
+        hipLaunchKernelGGL(k_cheb_step<double2>, dim3(stream_grid(n)), dim3(256), 0, s, (double2*)Vn,
+                           (const double2*)AV, (const double2*)V, (const double2*)Vm, a, c, n);
+    else if (p == Prec::FP32)
+        hipLaunchKernelGGL(k_cheb_step<float2>, dim3(stream_grid(n)), dim3(256), 0, s, (float2*)Vn,
+                           (const float2*)AV, (const float2*)V, (const float2*)Vm, a, c, n);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

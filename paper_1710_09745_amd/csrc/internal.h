@@ -106,11 +106,13 @@ hipError_t launch_pass_b(Prec prec, double2* X, const void* Qt, const void* P, v
 // Y <- Z + X M  (Z may be NULL = 0; X, Z may alias Y); X in precision px, Y/Z in py
 hipError_t launch_bmul(Prec px, const void* X, Prec py, const void* Z, void* Y, const double2* M,
                        int N, int Vh, const int* skip, hipStream_t s);
-// Y <- Z + X M with X of Nin columns, Y and Z of Nout, M Nin x Nout (leading dimension 64), FP64
-hipError_t launch_bmul_rect(const double2* X, const double2* Z, double2* Y, const double2* M, int Nin, int Nout,
-                            int Vh, const int* skip, hipStream_t s);
-// Vn = a (AV - c V) - Vm (Vm may be NULL), FP64, n pairs: one Chebyshev basis step
-hipError_t launch_cheb_step(double2* Vn, const double2* AV, const double2* V, const double2* Vm, double a, double c,
+// Y <- Z + X M with X of Nin columns in precision px (FP64 or FP32), Y and Z of Nout
+// FP64 columns, M Nin x Nout (leading dimension 64)
+hipError_t launch_bmul_rect(Prec px, const void* X, const double2* Z, double2* Y, const double2* M, int Nin,
+                            int Nout, int Vh, const int* skip, hipStream_t s);
+// Vn = a (AV - c V) - Vm (Vm may be NULL), FP64 or FP32 storage, n pairs: one
+// Chebyshev basis step
+hipError_t launch_cheb_step(Prec p, void* Vn, const void* AV, const void* V, const void* Vm, double a, double c,
                             long n, hipStream_t s);
 // v = w / *nrm, FP64, n pairs (*nrm read on the device)
 hipError_t launch_scale_inv(double2* v, const double2* w, const double* nrm, long n, hipStream_t s);

@@ -118,3 +118,60 @@ def test_restart_from_true_residual():
     assert res.max() <= 5e-14
     if info["rc"] == bcg.OK:
         assert res.max() <= 1.01e-14
+
+
+@pytest.mark.parametrize("s,n,k", [(1, 4, 3), (2, 4, 3), (3, 5, 2), (2, 16, 2)])
+def test_fp32_iterates_track_oracle(prob, s, n, k):
+    """FP32 storage of V, A V, P and A P (FP32 links and arithmetic in the basis
+    apply; FP64 X, R and Grams), no reliable updates: the iterate after k outer
+    iterations stays within a small multiple of FP32's unit roundoff of the oracle's
+    emulation of the same storage (its apply rounds the input, the odd-parity
+    intermediate and the output to binary32, the GPU's also rounds inside the stencil
+    sums), and of the FP64 iterate."""
+    from test_oracle_sstep import _fp32_storage
+
+    fat, lng, B, op, lam = prob
+    Bn = B[:n]
+    ctx = context(DIMS, True, fat, lng, MASS, tol=1e-14, prec="fp32", ru_delta=0.0, max_iter=k * s)
+    print(f"[case] s-step fp32 s={s} n={n} outer={k}", flush=True)
+    X, info = ctx.solve_sstep(to_dev(Bn), s, lam[0], lam[1], raise_on_error=False)
+    assert info["rc"] == bcg.ERR_NOT_CONVERGED and info["iters"] == k * s
+    rnd, As = _fp32_storage(op)
+    Xe, _ = oracle.sstep_block_cg(op.apply, Bn, s, 1e-14, lam, max_outer=k, sloppy=rnd, apply_sloppy=As)
+    Xo, _ = oracle.sstep_block_cg(op.apply, Bn, s, 1e-14, lam, max_outer=k)
+    Xg = X.cpu().numpy()
+    eps = 2.0 ** -24
+    e_emul, e64 = col_rel_err(Xg, Xe).max(), col_rel_err(Xg, Xo).max()
+    print(f"fp32 s-step: error against the emulated oracle {e_emul:.2e}, against FP64 {e64:.2e}")
+    assert e_emul <= 200 * eps
+    assert e64 <= 200 * eps
+
+
+@pytest.mark.parametrize("s", [1, 2])
+def test_fp32_solve_with_reliable_updates(s):
+    """FP32 storage with reliable updates every 10x drop reaches 1e-8 by the oracle's
+    FP64 operator; the step count stays within the bound the oracle shows for the
+    s-step recurrence in FP32 storage against blockCGrQ in the same storage."""
+    dims = (8, 8, 8, 8)
+    fat, lng, B = inputs(dims, True, 8, 6500)
+    m = 0.05
+    ctx = context(dims, True, fat, lng, m, tol=1e-8, prec="fp32", ru_delta=0.1, max_iter=20000)
+    print(f"[case] s-step fp32 solve s={s} n=8 8^4", flush=True)
+    X, info = ctx.solve_sstep(to_dev(B), s)
+    Xb, ib = ctx.solve(to_dev(B))
+    op = oracle.Operator(dims, fat, lng, m)
+    res = true_rel_res(op, B, X.cpu().numpy())
+    print(f"fp32 s-step s={s}: {info['iters']} steps, {info['reliable_updates']} reliable updates, "
+          f"restarts {info['restarts']}; blockCGrQ fp32 {ib['iters']} iterations; max res {res.max():.2e}")
+    assert res.max() <= 1e-8
+    assert np.allclose(res, info["true_rel_res"], rtol=1e-3, atol=1e-14)
+    assert info["reliable_updates"] >= 1
+    assert info["iters"] <= 1.8 * ib["iters"] + s
+
+
+def test_16bit_storage_refused(prob):
+    fat, lng, B, op, lam = prob
+    for prec in ("fp16", "bf16", "fix16"):
+        ctx = context(DIMS, True, fat, lng, MASS, tol=1e-10, prec=prec)
+        X, info = ctx.solve_sstep(to_dev(B[:4]), 2, raise_on_error=False)
+        assert info["rc"] == bcg.ERR_ARG
