@@ -178,3 +178,17 @@ def test_fp32_storage_with_reliable_updates(improved, n, m, s):
     assert info.iters <= 1.8 * ib.iters + s
     _, i0 = oracle.sstep_block_cg(op.apply, B, s, 1e-8, lam, max_outer=2000 // s, sloppy=rnd, apply_sloppy=As)
     assert i0.restarts >= 1 and i0.iters > info.iters
+
+
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_fp32_storage_iterates_stay_near_fp64(p1, s):
+    """A few outer iterations in emulated FP32 storage move the iterate by a small
+    multiple of FP32's unit roundoff from the FP64 iterate, and by more than FP64
+    rounding: the storage rounding is applied, and nothing else changes."""
+    op, B, Ad, lam = p1
+    rnd, As = _fp32_storage(op)
+    ref, _ = oracle.sstep_block_cg(op.apply, B, s, 1e-14, lam, max_outer=2)
+    X, info = oracle.sstep_block_cg(op.apply, B, s, 1e-14, lam, max_outer=2, sloppy=rnd, apply_sloppy=As)
+    assert info.outer == 2 and info.reliable_updates == 0
+    err = np.linalg.norm(oracle.to_mat(X - ref)) / np.linalg.norm(oracle.to_mat(ref))
+    assert 1e-12 < err <= 200 * 2.0 ** -24
