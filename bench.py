@@ -9,7 +9,8 @@ the final FP64 true-residual check), with inputs already resident in HBM.
 Printed: ONE JSON line with the metric (solve time per right-hand side, lower
 is better), the CG-baseline time per right-hand side on the same operator and
 tolerance, the roofline of the dominant kernel (algorithmic bytes over its
-average launch time measured with HIP events on the solver's stream), and the
+average launch time, from HIP start / stop events carried by each hop dispatch on
+the solver's stream), and the
 CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -238,7 +239,7 @@ def main():
           f"max true rel res={info['max_true_rel_res']:.2e}; dominant kernel {dominant}",
           file=sys.stderr, flush=True)
 
-    # timed region: K block solves; only the dominant kernel is bracketed by events
+    # timed region: K block solves; only the dominant kernel is timed by events
     ctx.set_profiling([dominant])
     ctx.profile_reset()
     torch.cuda.synchronize()

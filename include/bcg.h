@@ -320,10 +320,13 @@ enum { BCG_OPT_HOP_TR = 0, BCG_OPT_HOP_TPB = 1, BCG_OPT_HOP_PIPELINE = 2, BCG_OP
 int bcg_set_option(bcg_ctx *ctx, int option, int value);
 
 /* Per-kernel timing with HIP events on the context's stream.  mask: bit set of
- * BCG_K_* kernels to time (0 = off).  While on, each launch of a selected
- * kernel is bracketed by two events; bcg_kernel_time returns the number of
- * timed launches and their summed duration in milliseconds since the last
- * bcg_profile_reset, after synchronising the stream. */
+ * BCG_K_* kernels to time (0 = off).  While on, each hop launch carries a start
+ * and a stop event in its own dispatch (hipExtLaunchKernelGGL), which time the
+ * kernel alone; the other classes, whose calls may launch several kernels, are
+ * bracketed by two events recorded on the stream around the call.
+ * bcg_kernel_time returns the number of timed launches and their summed
+ * duration in milliseconds since the last bcg_profile_reset, after
+ * synchronising the stream. */
 enum {
     BCG_K_HOP_OE = 0, BCG_K_HOP_EO = 1, BCG_K_GRAM = 2, BCG_K_REDUCE = 3, BCG_K_SMALL = 4,
     BCG_K_PASS_A = 5, BCG_K_PASS_B = 6, BCG_K_CG_VEC = 7, BCG_K_CONVERT = 8, BCG_K_OTHER = 9,

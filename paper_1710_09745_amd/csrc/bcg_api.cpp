@@ -24,6 +24,10 @@
 
 using namespace bcg;
 
+namespace bcg {
+thread_local LaunchTiming g_launch_timing;
+}
+
 namespace {
 
 struct Buf {
@@ -179,17 +183,39 @@ struct GraphPair {
     }
 };
 
+// Per-kernel timing.  A scope that makes several launches is bracketed by two
+// events on the stream.  A single-launch scope (the hops) hands its events to the
+// launch itself (BCG_TIMED_LAUNCH), so that they time the dispatch and not the
+// event packets and cache write-back around it.
 struct Prof {
     bcg_ctx* ctx;
     int kid;
-    hipEvent_t a = nullptr;
-    Prof(bcg_ctx* c, int k) : ctx(c), kid(k) {
+    hipEvent_t a = nullptr, b1 = nullptr;
+    Prof(bcg_ctx* c, int k, bool single_launch = false) : ctx(c), kid(k) {
         if (ctx->prof_mask & (1u << kid)) {
             a = prof_event(ctx);
+            if (a && single_launch) {
+                b1 = prof_event(ctx);
+                if (b1) {
+                    g_launch_timing = LaunchTiming{a, b1, false};
+                    return;
+                }
+            }
             if (a) (void)hipEventRecord(a, ctx->stream);
         }
     }
     ~Prof() {
+        if (b1) {
+            const bool used = g_launch_timing.used;
+            g_launch_timing = LaunchTiming{};
+            if (used) {
+                ctx->pending.push_back(ProfEvent{kid, a, b1});
+            } else {
+                ctx->pool.push_back(a);
+                ctx->pool.push_back(b1);
+            }
+            return;
+        }
         if (a) {
             hipEvent_t b = prof_event(ctx);
             if (b) {
@@ -251,7 +277,7 @@ int hop(bcg_ctx* ctx, Prec p, int out_parity, const void* in, void* out, const v
     const void* Wp = (p == Prec::FP64) ? ctx->W64[out_parity] : ctx->Wsl[out_parity];
     HopShape h = shape(ctx, p, N, partials != nullptr);
     if (epi == EPI_MASS_DOT_) h = HopShape{1, 1, h.pf, 1};  // the CG path: one column, direction split
-    Prof pr(ctx, out_parity == 1 ? BCG_K_HOP_OE : BCG_K_HOP_EO);
+    Prof pr(ctx, out_parity == 1 ? BCG_K_HOP_OE : BCG_K_HOP_EO, true);
     HIPCK(launch_hop(p, ctx->nl, Wp, in, out, ctr, 4.0 * ctx->mass * ctx->mass, N, ctx->g,
                      out_parity, epi, h, halt, dot, partials, ctx->hopq, ctx->stream));
     return BCG_OK;

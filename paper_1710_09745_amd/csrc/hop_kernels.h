@@ -420,7 +420,7 @@ static void launch_hop_g(const void* W, const void* in, void* out, const void* c
         }
     }
 #define HOP_GO(E)                                                                                      \
-    hipLaunchKernelGGL((k_hop<S, TR, NL, E, PF, NB, GR>), grid, dim3(256), lds, s, (const P*)W, Ws,        \
+    BCG_TIMED_LAUNCH((k_hop<S, TR, NL, E, PF, NB, GR>), grid, dim3(256), lds, s, (const P*)W, Ws,          \
                        (const P*)in, ins, (P*)out, outs, (const P*)ctr, ctrs, m2, N, g, out_parity, spb, \
                        ntg, halt, dot, partials, q)
     if (epi == EPI_PLAIN) HOP_GO(EPI_PLAIN);
@@ -467,7 +467,7 @@ static void launch_hop_ls(const void* W, const void* in, void* out, const void* 
     float* outs = scale(out, N, 3);
     const float* ctrs = scale(ctr, N, 3);
 #define HOP_LS(E)                                                                                        \
-    hipLaunchKernelGGL((k_hop_ls<S, TR, NL, E, PF>), grid, dim3(256), 0, s, (const P*)W, Ws, (const P*)in, \
+    BCG_TIMED_LAUNCH((k_hop_ls<S, TR, NL, E, PF>), grid, dim3(256), 0, s, (const P*)W, Ws, (const P*)in,   \
                        ins, (P*)out, outs, (const P*)ctr, ctrs, m2, N, g, out_parity, ntiles, tpw, halt, dot)
     if (epi == EPI_PLAIN) HOP_LS(EPI_PLAIN);
     else if (epi == EPI_MASS) HOP_LS(EPI_MASS);

@@ -1,11 +1,35 @@
 // Host-side declarations shared by the library's translation units: the
 // launchers of every gfx950 kernel and the constants of the solver's layouts.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
 
 namespace bcg {
+
+// Timing events for the next kernel launch on the calling thread.  A launcher that
+// finds them set issues its kernel with hipExtLaunchKernelGGL, so that the two events
+// carry the start and end of that dispatch itself (no queue gap or end-of-kernel
+// cache write-back between an event and the kernel), marks them used and clears
+// them.  Set by the library's per-kernel profiler around single-launch calls.
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool used = false;
+};
+extern thread_local LaunchTiming g_launch_timing;
+
+#define BCG_TIMED_LAUNCH(KERNEL, GRID, BLOCK, LDS, STREAM, ...)                                         \
+    do {                                                                                               \
+        if (::bcg::g_launch_timing.start != nullptr) {                                                 \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, STREAM, ::bcg::g_launch_timing.start,      \
+                                  ::bcg::g_launch_timing.stop, 0u, __VA_ARGS__);                       \
+            ::bcg::g_launch_timing.used = true;                                                        \
+            ::bcg::g_launch_timing.start = ::bcg::g_launch_timing.stop = nullptr;                      \
+        } else {                                                                                       \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, STREAM, __VA_ARGS__);                         \
+        }                                                                                              \
+    } while (0)
 
 enum class Prec { FP64 = 0, FP32 = 1, FP16 = 2, BF16 = 3, FX16 = 4 };
 
