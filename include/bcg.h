@@ -285,8 +285,10 @@ int bcg_set_stability(bcg_ctx *ctx, int ru_window, int stall_limit, int qr_passe
  *                         Gram kernels instead, with no error
  *   BCG_OPT_HOP_KERNEL    1: lane-split hop (the four lane groups of a wave take
  *                         one direction each for 16 sites), 2: site-parallel hop
- *                         (lane groups share sites, BCG_OPT_HOP_TPB); default by
- *                         lattice size
+ *                         (lane groups share sites, BCG_OPT_HOP_TPB), 3: lane-split
+ *                         hop with two lane groups of 32 sites taking two
+ *                         directions each; default by lattice size and storage
+ *                         (3 in place of 1 below FP64 storage)
  *   BCG_OPT_GRAM_KERNEL   1: Gram products on the matrix cores (FP64 MFMA) for
  *                         N > 8, 2: on the vector ALUs
  *   BCG_OPT_SMALL_THREADS threads (64, 256, 1024) of the one-workgroup N x N

@@ -108,12 +108,17 @@ HopShape hop_shape(Prec p, int N, int tr, int tpb, int pf, int kernel, const Geo
     HopShape h;
     // default kernel: the site-parallel kernel when its grid fills the chip four
     // times over, the lane-split kernel on smaller lattices (measured on MI355X:
-    // 16^4 and 32^3 x 64 at N = 4 ... 64)
+    // 16^4 and 32^3 x 64 at N = 4 ... 64); below 16 bytes per stored complex number
+    // the lane-split kernel takes runs of 32 sites, so that a load instruction covers
+    // whole cache lines (16^4, N = 16, FP32: 27.0 / 29.4 us against 29.6 / 32.6 us
+    // per hop; FP64 even)
     const bool small_lattice = g.Vh / 128 < 4 * 256;
     if (fused) h.split = 0;
     else if (kernel == 1) h.split = 1;
+    else if (kernel == 3) h.split = 2;
     else if (kernel == 2) h.split = 0;
-    else h.split = (small_lattice && N > 1) || N == 1 ? 1 : 0;
+    else if (N == 1) h.split = 1;
+    else h.split = small_lattice ? (p == Prec::FP64 ? 1 : 2) : 0;
     if (h.split) {
         h.tpb = 1;
         h.pf = pf > 0 ? 1 : 0;
@@ -126,7 +131,6 @@ HopShape hop_shape(Prec p, int N, int tr, int tpb, int pf, int kernel, const Geo
     // tpb x TR columns and N > 16 takes several sweeps over the lattice, one per
     // group of 16 columns (narrower sweeps re-read the links more often than they
     // save in neighbour re-fetches: measured slower at 32^3 x 64)
-    (void)p;
     h.pf = 1;
     if (N <= 1) { h.tr = 1; h.tpb = 1; }
     else if (N <= 2) { h.tr = 2; h.tpb = 1; }

@@ -256,20 +256,23 @@ k_hop(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
     }
 }
 
-// Lane-split hop: lane l of a wave takes site l % 16 of a block of 16 consecutive
-// output sites and direction mu = l / 16, and applies the NL/4 folded matrices of
-// that direction (forward and backward, one and three hops) to a register tile of
-// TR right-hand sides.  The four direction sums of a site meet through a
-// butterfly of cross-lane exchanges (xor 16, then xor 32): every lane of the site
-// ends with the same bits, so the result does not depend on the lane order.  The
-// waves of a workgroup are tpw right-hand-side tiles of the same sites (their link
-// loads meet in the CU's L1) and 4 / tpw blocks of 16 sites.  The grid is (site
-// blocks) x (tile groups), walked so that each XCD takes a contiguous range of
-// site blocks with all their tile groups one after the other.  The folded links
-// are addressed with one 32-bit byte offset per lane: NL * 9 * Vh * bytes < 4 GiB
-// (checked by the launcher).
+// Lane-split hop: lane l of a wave takes site l % SR of a block of SR consecutive
+// output sites and the 64 / SR directions mu = (l / SR) * DL ... (l / SR) * DL + DL - 1
+// (DL = SR / 16), and applies the NL/4 folded matrices of each of its directions
+// (forward and backward, one and three hops) to a register tile of TR right-hand
+// sides.  SR = 16: one direction per lane, four per wave; SR = 32: two per lane, so
+// each load instruction covers two runs of 32 sites instead of four of 16 (fewer
+// cache lines per instruction) for twice the hops per lane.  The direction sums of
+// a site meet through a butterfly of cross-lane exchanges (xor SR, ..., xor 32):
+// every lane of the site ends with the same bits, so the result does not depend on
+// the lane order.  The waves of a workgroup are tpw right-hand-side tiles of the
+// same sites (their link loads meet in the CU's L1) and 4 / tpw blocks of SR sites.
+// The grid is (site blocks) x (tile groups), walked so that each XCD takes a
+// contiguous range of site blocks with all their tile groups one after the other.
+// The folded links are addressed with one 32-bit byte offset per lane:
+// NL * 9 * Vh * bytes < 4 GiB (checked by the launcher).
 // EPI_MASS_DOT (TR = 1): dot[blockIdx.x] = Re <ctr, out> over the workgroup's sites.
-template <typename S, int TR, int NL, int EPI, bool PF>
+template <typename S, int TR, int NL, int EPI, bool PF, int SR>
 __global__ void __launch_bounds__(256)
 k_hop_ls(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
          const typename S::pair* __restrict__ in, const float* __restrict__ ins,
@@ -277,31 +280,31 @@ k_hop_ls(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
          const typename S::pair* __restrict__ ctr, const float* __restrict__ ctrs,
          double m2d, int N, Geom g, int out_parity, int ntiles, int tpw, const int* __restrict__ halt,
          double* __restrict__ dot) {
+    static_assert(SR == 16 || SR == 32, "site runs of 16 or 32");
     using R = typename S::real;
-    constexpr int NJ = NL / 4;  // hops per direction
+    constexpr int NJ = NL / 4;   // hops per direction
+    constexpr int NG = 64 / SR;  // direction groups per wave
+    constexpr int DL = 4 / NG;   // directions per lane
     if (halt != nullptr && *halt) return;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int sgn = 4 / tpw;                        // blocks of 16 sites per workgroup
-    const int nsb = (g.Vh + 16 * sgn - 1) / (16 * sgn);
+    const int sgn = 4 / tpw;                        // blocks of SR sites per workgroup
+    const int nsb = (g.Vh + SR * sgn - 1) / (SR * sgn);
     const int ntg = (ntiles + tpw - 1) / tpw;       // tile groups
     int sb, tg;
-    xcd_task_tm(blockIdx.x, nsb, ntg, blocks_per_slice(g, 16 * sgn), sb, tg);
+    xcd_task_tm(blockIdx.x, nsb, ntg, blocks_per_slice(g, SR * sgn), sb, tg);
     const int tile_w = tg * tpw + w % tpw;
     const bool tile_ok = tile_w < ntiles;
     const int r0 = (tile_ok ? tile_w : ntiles - 1) * TR;
-    const int s16 = lane & 15, mu = lane >> 4;
+    const int s16 = lane % SR, grp = lane / SR;
     const long Vh = g.Vh;
     const unsigned plane = (unsigned)Vh * S::bytes;
-    const int i0 = sb * 16 * sgn + (w / tpw) * 16 + s16;
+    const int i0 = sb * SR * sgn + (w / tpw) * SR + s16;
     const bool live = i0 < g.Vh;
     const int i = live ? i0 : g.Vh - 1;  // spare lanes work on the last site and store nothing
     int x[4];
     site_coords(g, i, out_parity, x);
     const int lex = x[0] + g.L[0] * (x[1] + g.L[1] * (x[2] + g.L[2] * x[3]));
-    const int sm = mu == 0 ? 1 : (mu == 1 ? g.L[0] : (mu == 2 ? g.L[0] * g.L[1] : g.L[0] * g.L[1] * g.L[2]));
-    const int xm = mu == 0 ? x[0] : (mu == 1 ? x[1] : (mu == 2 ? x[2] : x[3]));
-    const int Lm = mu == 0 ? g.L[0] : (mu == 1 ? g.L[1] : (mu == 2 ? g.L[2] : g.L[3]));
     rsrc_t vin[TR], vins[TR];
 #pragma unroll
     for (int r = 0; r < TR; ++r) {
@@ -316,56 +319,64 @@ k_hop_ls(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
     for (int r = 0; r < TR; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[r][c] = c2<R>(0, 0);
-    auto fetch = [&](HopOperands<S, TR>& o, int j) {
-        const int hop = (NL == 16 && (j & 2)) ? 3 : 1;
-        const int d = (j & 1) ? -hop : hop;
-        int v = xm + d;
-        int nbl = lex + d * sm;
-        const int wrap = Lm * sm;
-        if (v >= Lm) { v -= Lm; nbl -= wrap; }
-        if (v >= Lm) nbl -= wrap;
-        if (v < 0) { v += Lm; nbl += wrap; }
-        if (v < 0) nbl += wrap;
-        const unsigned nb = (unsigned)nbl >> 1;
-        const unsigned k = (unsigned)(mu * NJ + j);
-        buf_group<S, 9, AUX_NONE>(wr, wsr, (k * 9u * (unsigned)Vh + (unsigned)i) * S::bytes,
-                                (k * (unsigned)Vh + (unsigned)i) * 4u, plane, o.w);
 #pragma unroll
-        for (int r = 0; r < TR; ++r) buf_group<S, 3, AUX_NONE>(vin[r], vins[r], nb * S::bytes, nb * 4u, plane, o.v[r]);
-    };
-    if constexpr (!PF) {
+    for (int dd = 0; dd < DL; ++dd) {
+        const int mu = grp * DL + dd;
+        const int sm = mu == 0 ? 1 : (mu == 1 ? g.L[0] : (mu == 2 ? g.L[0] * g.L[1] : g.L[0] * g.L[1] * g.L[2]));
+        const int xm = mu == 0 ? x[0] : (mu == 1 ? x[1] : (mu == 2 ? x[2] : x[3]));
+        const int Lm = mu == 0 ? g.L[0] : (mu == 1 ? g.L[1] : (mu == 2 ? g.L[2] : g.L[3]));
+        auto fetch = [&](HopOperands<S, TR>& o, int j) {
+            const int hop = (NL == 16 && (j & 2)) ? 3 : 1;
+            const int d = (j & 1) ? -hop : hop;
+            int v = xm + d;
+            int nbl = lex + d * sm;
+            const int wrap = Lm * sm;
+            if (v >= Lm) { v -= Lm; nbl -= wrap; }
+            if (v >= Lm) nbl -= wrap;
+            if (v < 0) { v += Lm; nbl += wrap; }
+            if (v < 0) nbl += wrap;
+            const unsigned nb = (unsigned)nbl >> 1;
+            const unsigned k = (unsigned)(mu * NJ + j);
+            buf_group<S, 9, AUX_NONE>(wr, wsr, (k * 9u * (unsigned)Vh + (unsigned)i) * S::bytes,
+                                    (k * (unsigned)Vh + (unsigned)i) * 4u, plane, o.w);
+#pragma unroll
+            for (int r = 0; r < TR; ++r)
+                buf_group<S, 3, AUX_NONE>(vin[r], vins[r], nb * S::bytes, nb * 4u, plane, o.v[r]);
+        };
+        if constexpr (!PF) {
 #pragma unroll 1
-        for (int j = 0; j < NJ; ++j) {
-            HopOperands<S, TR> o;
-            fetch(o, j);
-            hop_fma<S, TR>(o, acc);
-        }
-    } else {
+            for (int j = 0; j < NJ; ++j) {
+                HopOperands<S, TR> o;
+                fetch(o, j);
+                hop_fma<S, TR>(o, acc);
+            }
+        } else {
 #pragma unroll 1
-        for (int j = 0; j < NJ; j += 2) {
-            HopOperands<S, TR> o0, o1;
-            fetch(o0, j);
-            fetch(o1, j + 1);
-            hop_fma<S, TR>(o0, acc);
-            hop_fma<S, TR>(o1, acc);
+            for (int j = 0; j < NJ; j += 2) {
+                HopOperands<S, TR> o0, o1;
+                fetch(o0, j);
+                fetch(o1, j + 1);
+                hop_fma<S, TR>(o0, acc);
+                hop_fma<S, TR>(o1, acc);
+            }
         }
     }
-    // sum over the four directions of the site: xor 16 then xor 32
+    // sum over the direction groups of the site: xor SR, ..., xor 32
 #pragma unroll
     for (int r = 0; r < TR; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            acc[r][c].re += __shfl_xor(acc[r][c].re, 16, 64);
-            acc[r][c].im += __shfl_xor(acc[r][c].im, 16, 64);
-            acc[r][c].re += __shfl_xor(acc[r][c].re, 32, 64);
-            acc[r][c].im += __shfl_xor(acc[r][c].im, 32, 64);
-        }
-    // lane group mu finishes right-hand sides r = mu, mu + 4 of the tile
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int off = SR; off < 64; off <<= 1) {
+                acc[r][c].re += __shfl_xor(acc[r][c].re, off, 64);
+                acc[r][c].im += __shfl_xor(acc[r][c].im, off, 64);
+            }
+    // lane group grp finishes right-hand sides r = grp, grp + NG, ... of the tile
     const R m2 = (R)m2d;
     double mydot = 0.0;
 #pragma unroll
     for (int r = 0; r < TR; ++r) {
-        if ((r & 3) == mu && tile_ok && r0 + r < N) {
+        if ((r % NG) == grp && tile_ok && r0 + r < N) {
             C2<R> v[3] = {acc[r][0], acc[r][1], acc[r][2]};
             C2<R> z[3];
             if (EPI != EPI_PLAIN) {
@@ -385,7 +396,7 @@ k_hop_ls(const typename S::pair* __restrict__ W, const float* __restrict__ Ws,
         }
     }
     if (EPI == EPI_MASS_DOT) {
-        // TR == 1, tpw == 1: four waves of 16 sites each; lanes mu > 0 hold 0
+        // TR == 1, tpw == 1: four waves of SR sites each; lanes of groups > 0 hold 0
         __shared__ double red[4];
         for (int off = 32; off > 0; off >>= 1) mydot += __shfl_xor(mydot, off, 64);
         if (lane == 0) red[w] = mydot;
@@ -449,7 +460,7 @@ static void launch_hop_t(const void* W, const void* in, void* out, const void* c
 #undef HG
 }
 
-template <typename S, int TR, int NL, bool PF>
+template <typename S, int TR, int NL, bool PF, int SR>
 static void launch_hop_ls(const void* W, const void* in, void* out, const void* ctr, double m2, int N,
                           const Geom& g, int out_parity, int epi, const int* halt, double* dot, hipStream_t s) {
     using P = typename S::pair;
@@ -460,14 +471,14 @@ static void launch_hop_ls(const void* W, const void* in, void* out, const void* 
     const int ntiles = (N + TR - 1) / TR;
     const int tpw = ntiles < 4 ? (ntiles < 2 ? 1 : 2) : 4;
     const int sgn = 4 / tpw;
-    const long nsb = (Vh + 16 * sgn - 1) / (16 * sgn);
+    const long nsb = (Vh + SR * sgn - 1) / (SR * sgn);
     const dim3 grid((unsigned)(nsb * ((ntiles + tpw - 1) / tpw)));
     const float* Ws = scale(W, NL, 9);
     const float* ins = scale(in, N, 3);
     float* outs = scale(out, N, 3);
     const float* ctrs = scale(ctr, N, 3);
 #define HOP_LS(E)                                                                                        \
-    BCG_TIMED_LAUNCH((k_hop_ls<S, TR, NL, E, PF>), grid, dim3(256), 0, s, (const P*)W, Ws, (const P*)in,   \
+    BCG_TIMED_LAUNCH((k_hop_ls<S, TR, NL, E, PF, SR>), grid, dim3(256), 0, s, (const P*)W, Ws, (const P*)in, \
                        ins, (P*)out, outs, (const P*)ctr, ctrs, m2, N, g, out_parity, ntiles, tpw, halt, dot)
     if (epi == EPI_PLAIN) HOP_LS(EPI_PLAIN);
     else if (epi == EPI_MASS) HOP_LS(EPI_MASS);
@@ -481,8 +492,10 @@ static void launch_hop_nl(const void* W, const void* in, void* out, const void* 
                           const int* halt, double* dot, double2* partials, int* queue, hipStream_t s) {
     if (h.split) {
 #define HOP_DT(T)                                                                                        \
-    (h.pf ? launch_hop_ls<S, T, NL, true>(W, in, out, ctr, m2, N, g, out_parity, epi, halt, dot, s)      \
-          : launch_hop_ls<S, T, NL, false>(W, in, out, ctr, m2, N, g, out_parity, epi, halt, dot, s))
+    (h.split == 2 ? (h.pf ? launch_hop_ls<S, T, NL, true, 32>(W, in, out, ctr, m2, N, g, out_parity, epi, halt, dot, s)   \
+                          : launch_hop_ls<S, T, NL, false, 32>(W, in, out, ctr, m2, N, g, out_parity, epi, halt, dot, s))  \
+                  : (h.pf ? launch_hop_ls<S, T, NL, true, 16>(W, in, out, ctr, m2, N, g, out_parity, epi, halt, dot, s)   \
+                          : launch_hop_ls<S, T, NL, false, 16>(W, in, out, ctr, m2, N, g, out_parity, epi, halt, dot, s)))
         switch (h.tr) {
             case 1: HOP_DT(1); break;
             case 2: HOP_DT(2); break;

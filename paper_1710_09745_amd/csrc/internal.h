@@ -41,7 +41,7 @@ struct HopShape {
     int tr;     // right-hand sides per lane (register tile)
     int tpb;    // site-parallel kernel: lane groups per workgroup sharing the same sites
     int pf;     // 1: two folded matrices in flight per loop trip
-    int split;  // 1: direction-split kernel (four waves share 64 sites), 0: site-parallel
+    int split;  // 1: lane-split kernel (runs of 16 sites), 2: lane-split, runs of 32 sites, 0: site-parallel
     int queue_wpc = 0;  // site-parallel kernel: > 0 = per-XCD task queues, this many workgroups per CU
 };
 

@@ -316,11 +316,11 @@ def test_fused_gram_path_matches_oracle(prec, n):
 
 @pytest.mark.parametrize("kernel,tr,tpb,pf,cpt", [(2, 1, 4, 1, 1), (2, 2, 2, 0, 2), (2, 8, 1, 1, 4), (2, 4, 4, 1, 2),
                                                   (2, 8, 2, 1, 4), (1, 1, 0, 0, 1), (1, 2, 0, 1, 2), (1, 8, 0, 1, 4),
-                                                  (0, 0, 0, 0, 0)])
+                                                  (0, 0, 0, 0, 0), (3, 8, 0, 1, 4), (3, 4, 0, 0, 2), (3, 1, 0, 1, 1)])
 def test_launch_shapes_match_oracle(kernel, tr, tpb, pf, cpt):
-    """Both hop kernels (direction split, site-parallel) with every register tile,
-    lane-group and pipelining choice, and every pass column tile, give the same
-    operator and iterates."""
+    """The hop kernels (direction split with runs of 16 or 32 sites, site-parallel)
+    with every register tile, lane-group and pipelining choice, and every pass
+    column tile, give the same operator and iterates."""
     dims = (6, 6, 6, 6)
     n = 9
     fat, lng, B = inputs(dims, True, n, 6900)
