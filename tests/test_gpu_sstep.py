@@ -120,14 +120,15 @@ def test_restart_from_true_residual():
         assert res.max() <= 1.01e-14
 
 
-@pytest.mark.parametrize("s,n,k", [(1, 4, 3), (2, 4, 3), (3, 5, 2), (2, 16, 2)])
+@pytest.mark.parametrize("s,n,k", [(1, 4, 3), (2, 4, 3), (3, 5, 2), (2, 16, 2), (3, 11, 2), (4, 16, 2)])
 def test_fp32_iterates_track_oracle(prob, s, n, k):
     """FP32 storage of V, A V, P and A P (FP32 links and arithmetic in the basis
     apply; FP64 X, R and Grams), no reliable updates: the iterate after k outer
     iterations stays within a small multiple of FP32's unit roundoff of the oracle's
     emulation of the same storage (its apply rounds the input, the odd-parity
     intermediate and the output to binary32, the GPU's also rounds inside the stencil
-    sums), and of the FP64 iterate."""
+    sums), and of the FP64 iterate.  K = s N up to 32 takes the two Grams of
+    [V | P'], above it the five K-column Grams (two of them on the vector ALUs)."""
     from test_oracle_sstep import _fp32_storage
 
     fat, lng, B, op, lam = prob
