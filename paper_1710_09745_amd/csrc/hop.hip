@@ -111,13 +111,15 @@ HopShape hop_shape(Prec p, int N, int tr, int tpb, int pf, int kernel, const Geo
     // 16^4 and 32^3 x 64 at N = 4 ... 64); below 16 bytes per stored complex number
     // the lane-split kernel takes runs of 32 sites, so that a load instruction covers
     // whole cache lines (16^4, N = 16, FP32: 27.0 / 29.4 us against 29.6 / 32.6 us
-    // per hop; FP64 even)
+    // per hop; FP64 even); at N = 1 only on large lattices, where the grid of
+    // 128-site workgroups still fills the chip (32^3 x 64 FP32: 310 / 298 us against
+    // 337 / 330 us; 16^4: 10.3 / 10.0 against 9.2 / 8.2 us)
     const bool small_lattice = g.Vh / 128 < 4 * 256;
     if (fused) h.split = 0;
     else if (kernel == 1) h.split = 1;
     else if (kernel == 3) h.split = 2;
     else if (kernel == 2) h.split = 0;
-    else if (N == 1) h.split = 1;
+    else if (N == 1) h.split = (p == Prec::FP64 || small_lattice) ? 1 : 2;
     else h.split = small_lattice ? (p == Prec::FP64 ? 1 : 2) : 0;
     if (h.split) {
         h.tpb = 1;
