@@ -272,11 +272,23 @@ HopShape shape(bcg_ctx* ctx, Prec p, int N, bool fused) {
                      ctx->opt[BCG_OPT_HOP_KERNEL], ctx->g, fused, ctx->opt[BCG_OPT_HOP_SCHED]);
 }
 
+// The CG path's hop with the fused p^H A p: one column on the lane-split kernel, with
+// the run length (16 or 32 sites) that the one-column shape picks; it writes one dot
+// partial per workgroup of four runs.
+HopShape dot_shape(bcg_ctx* ctx, Prec p) {
+    const HopShape h = shape(ctx, p, 1, false);
+    return HopShape{1, 1, h.pf, h.split == 2 ? 2 : 1};
+}
+int dot_parts(bcg_ctx* ctx, Prec p) {
+    const long sites = dot_shape(ctx, p).split == 2 ? 128 : 64;
+    return (int)((ctx->Vh + sites - 1) / sites);
+}
+
 int hop(bcg_ctx* ctx, Prec p, int out_parity, const void* in, void* out, const void* ctr, int N,
         int epi, const int* halt, double* dot = nullptr, double2* partials = nullptr) {
     const void* Wp = (p == Prec::FP64) ? ctx->W64[out_parity] : ctx->Wsl[out_parity];
     HopShape h = shape(ctx, p, N, partials != nullptr);
-    if (epi == EPI_MASS_DOT_) h = HopShape{1, 1, h.pf, 1};  // the CG path: one column, direction split
+    if (epi == EPI_MASS_DOT_) h = dot_shape(ctx, p);
     Prof pr(ctx, out_parity == 1 ? BCG_K_HOP_OE : BCG_K_HOP_EO, true);
     HIPCK(launch_hop(p, ctx->nl, Wp, in, out, ctr, 4.0 * ctx->mass * ctx->mass, N, ctx->g,
                      out_parity, epi, h, halt, dot, partials, ctx->hopq, ctx->stream));
@@ -405,7 +417,7 @@ int cg_mixed(bcg_ctx* ctx, const double2* B64, double2* Ys, const double* bn, in
     CgState* st = ctx->d_cg;
     const int* halt = &st->halt;
     double* dot = ctx->nparts + ctx->dot_off;
-    const int nparts = hop_dot_blocks(ctx->g);
+    const int nparts = dot_parts(ctx, ps);
     HIPCK(launch_identity(M(ctx, M_ID), 1, s));
     int status = BCG_OK;
     for (int i = 0; i < N; ++i) {
@@ -1186,7 +1198,7 @@ int bcg_solve_cg(bcg_ctx* ctx, const void* B, void* Xout, int nrhs, bcg_stats* s
     int status = BCG_OK;
     int total_iters = 0, restarts = 0;
     double tr[MAXN];
-    const int nparts = hop_dot_blocks(ctx->g);
+    const int nparts = dot_parts(ctx, Prec::FP64);
     if (ctx->sloppy != Prec::FP64) {
         status = cg_mixed(ctx, B64, Xs, bn, N, tr, &total_iters, &restarts);
         if (status == BCG_ERR_HIP || status == BCG_ERR_NOMEM) return status;

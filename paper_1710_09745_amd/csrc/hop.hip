@@ -113,7 +113,8 @@ HopShape hop_shape(Prec p, int N, int tr, int tpb, int pf, int kernel, const Geo
     // whole cache lines (16^4, N = 16, FP32: 27.0 / 29.4 us against 29.6 / 32.6 us
     // per hop; FP64 even); at N = 1 only on large lattices, where the grid of
     // 128-site workgroups still fills the chip (32^3 x 64 FP32: 310 / 298 us against
-    // 337 / 330 us; 16^4: 10.3 / 10.0 against 9.2 / 8.2 us)
+    // 337 / 330 us; 16^4: 10.3 / 10.0 against 9.2 / 8.2 us); the CG path's hop with
+    // the fused dot takes the same run length
     const bool small_lattice = g.Vh / 128 < 4 * 256;
     if (fused) h.split = 0;
     else if (kernel == 1) h.split = 1;
@@ -185,7 +186,8 @@ extern template void launch_hop_s<B16>(int, const void*, const void*, void*, con
 extern template void launch_hop_s<X16>(int, const void*, const void*, void*, const void*, double, int, const Geom&,
                                        int, int, const HopShape&, const int*, double*, double2*, int*, hipStream_t);
 
-int hop_dot_blocks(const Geom& g) { return (g.Vh + 63) / 64; }  // lane-split kernel, N = 1
+// dot partials of the one-column lane-split hop: at most one per 64 sites (runs of 16)
+int hop_dot_blocks(const Geom& g) { return (g.Vh + 63) / 64; }
 
 HopQueue hop_queue_layout(const Geom& g, int spb, int* ctr) {
     HopQueue q{};

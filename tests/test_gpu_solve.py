@@ -112,6 +112,31 @@ def test_mixed_cg_baseline_meets_tolerance(prec):
     assert info["iters"] <= 1.5 * i64["iters"] + 30
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-8)])
+def test_cg_hop_run_lengths_agree(prec, tol):
+    """The CG baseline's hop with its fused p^H A p on runs of 32 sites (128-site
+    workgroups and half as many dot partials; the default below FP64 on large
+    lattices, chosen here explicitly) and on runs of 16 sites: both meet the
+    tolerance by the oracle's operator, in the same iteration counts, and in FP64 the
+    solutions agree to the rounding bound."""
+    dims = (8, 8, 8, 8)
+    fat, lng, B = inputs(dims, True, 2, 6070)
+    m = 0.1
+    op = oracle.Operator(dims, fat, lng, m)
+    out = {}
+    for kernel in (1, 3):
+        ctx = context(dims, True, fat, lng, m, tol=tol, prec=prec)
+        ctx.set_option("hop_kernel", kernel)
+        print(f"[case] CG {prec} hop_kernel={kernel}", flush=True)
+        X, info = ctx.solve_cg(to_dev(B))
+        X = X.cpu().numpy()
+        assert true_rel_res(op, B, X).max() <= tol
+        out[kernel] = (X, info["iters"])
+    assert abs(out[1][1] - out[3][1]) <= 4
+    if prec == "fp64":
+        assert col_rel_err(out[3][0], out[1][0]).max() <= kappa_bound(op) * 2e-10
+
+
 @pytest.mark.parametrize("k", [1, 3, 7])
 def test_pseudo_block_iterates_match_oracle_cg(k):
     """Pseudo-block CG after k lockstep iterations: every column is the oracle's
